@@ -1,0 +1,109 @@
+"""S-format operations on dense arrays (zero outside the pattern).
+
+* ``masked_product``: the formatted product (Section 4.1, Theorem (product),
+  eq. (product)).  The paper stresses that it is exact on the compression
+  pattern: c_ij = sum_k a_ik b_kj for (i, j) in S, where only k with
+  (i, k) and (k, j) in S contribute because A and B vanish elsewhere.  The sum
+  in eq. (product) runs over the samplets of all levels; it is read as running
+  over all N basis indices, the root's scaling distributions included.
+* ``axpy``: formatted addition (Section 4.1).
+* ``newton_schulz``: X_0 = alpha I, Y = P_S(A X), Z = 2I - Y, X <- P_S(X Z).
+  The paper inverts A = K + mu I by selected inversion (Section 4.2); its
+  regularised-inverse lemma (eq. (perturbation)) shows the inverse is
+  compressible on the pattern of K.  The iteration here keeps every iterate
+  and every intermediate product on that pattern.
+* ``ns_backward``: reverse mode of the iteration for f = y^T X_K y.
+* ``error_estimator``: e_F(A) = ||A X||_F / ||X||_F with X in U[0,1]^{N x 10}
+  (Section 5.1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def masked_product(a: np.ndarray, b: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    return np.where(mask, a @ b, 0.0)
+
+
+def axpy(alpha: float, x, beta: float, y: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """alpha X + beta Y on the pattern; X = None means the identity."""
+    if x is None:
+        x = np.eye(y.shape[0])
+    return np.where(mask, alpha * x + beta * y, 0.0)
+
+
+def residual(a: np.ndarray, x: np.ndarray, mask: np.ndarray) -> float:
+    n = a.shape[0]
+    e = np.eye(n) - masked_product(a, x, mask)
+    return float(np.sqrt(np.sum(e * e)) / np.sqrt(n))
+
+
+def newton_schulz(a: np.ndarray, mask: np.ndarray, iters: int, alpha0: float):
+    """Returns (X_iters, residuals r_0..r_iters, iterates X_0..X_iters)."""
+    n = a.shape[0]
+    eye = np.eye(n)
+    x = np.where(mask, alpha0 * eye, 0.0)
+    xs = [x]
+    res = []
+    for _ in range(iters):
+        y = masked_product(a, x, mask)
+        e = eye - y
+        res.append(float(np.sqrt(np.sum(e * e)) / np.sqrt(n)))
+        z = np.where(mask, 2.0 * eye - y, 0.0)
+        x = masked_product(x, z, mask)
+        xs.append(x)
+    res.append(residual(a, x, mask))
+    return x, res, xs
+
+
+def quadform(x: np.ndarray, y: np.ndarray) -> float:
+    return float(y @ x @ y)
+
+
+def ns_backward(a: np.ndarray, mask: np.ndarray, xs: list, xbar_final: np.ndarray) -> np.ndarray:
+    """Adjoint of X_K(A) for the loss seed X_K-bar; returns A-bar on the pattern.
+
+    Forward step k: Y_k = P(A X_k), Z_k = 2I - Y_k, X_{k+1} = P(X_k Z_k).
+    The adjoint of C = P(U V) with respect to U is P(C-bar V^T) and with respect
+    to V is P(U^T C-bar) (mask applied since only pattern entries are free).
+    """
+    n = a.shape[0]
+    eye = np.eye(n)
+    abar = np.zeros_like(a)
+    xbar = xbar_final
+    for k in range(len(xs) - 2, -1, -1):
+        xk = xs[k]
+        yk = masked_product(a, xk, mask)
+        zk = np.where(mask, 2.0 * eye - yk, 0.0)
+        xbar_k = masked_product(xbar, zk.T, mask)
+        zbar = masked_product(xk.T, xbar, mask)
+        ybar = -zbar
+        abar += masked_product(ybar, xk.T, mask)
+        xbar_k += masked_product(a.T, ybar, mask)
+        xbar = xbar_k
+    return abar
+
+
+def gp_objective_and_grad(a: np.ndarray, da: np.ndarray, mask: np.ndarray, y: np.ndarray,
+                          iters: int, alpha0: float):
+    """f = y^T X_K(A) y and df/dl = <A-bar, dA/dl>_S."""
+    xk, res, xs = newton_schulz(a, mask, iters, alpha0)
+    f = quadform(xk, y)
+    seed = np.where(mask, np.outer(y, y), 0.0)
+    abar = ns_backward(a, mask, xs, seed)
+    return f, float(np.sum(abar * da)), res
+
+
+def column_local_inverse(a: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """The X with support S and P_S(A X) = I: column j solves A[S_j, S_j] x = e_j on S_j."""
+    n = a.shape[0]
+    x = np.zeros_like(a)
+    for j in range(n):
+        s = np.nonzero(mask[:, j])[0]
+        rhs = (s == j).astype(np.float64)
+        x[s, j] = np.linalg.solve(a[np.ix_(s, s)], rhs)
+    return x
+
+
+def error_estimator(a: np.ndarray, xprobe: np.ndarray) -> float:
+    return float(np.linalg.norm(a @ xprobe) / np.linalg.norm(xprobe))

@@ -1,0 +1,180 @@
+"""Pins of the oracle's operations: formatted product, addition, Newton-Schulz,
+adjoints and the Gaussian-process lengthscale gradient."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import compress, native, ops, pattern, samplets, tree
+
+
+def _small(n=256, d=2, leaf=16, q=1, eta=1.0, seed=21):
+    t = tree.build_tree(synth.points_cube(n, d, seed), leaf)
+    b = samplets.build_samplets(t, q)
+    rp, col = pattern.entry_csr(b, pattern.block_pattern(t, eta))
+    return t, b, rp, col, pattern.dense_mask(rp, col, n)
+
+
+def _rand_on(mask, seed):
+    n = mask.shape[0]
+    i, j = np.nonzero(mask)
+    v = np.zeros(mask.shape)
+    v[i, j] = 2.0 * synth.pair_uniform(seed, i, j, n) - 1.0
+    return v
+
+
+def test_product_brute_force_tiny():
+    # triple loop over (i, j) in S and k in S_i cap S_j, pure Python
+    t, b, rp, col, mask = _small(n=64, leaf=8, eta=0.8)
+    a, bb = _rand_on(mask, 1), _rand_on(mask, 2)
+    rows = [set(col[rp[i]:rp[i + 1]].tolist()) for i in range(64)]
+    ref = np.zeros_like(a)
+    for i in range(64):
+        for j in rows[i]:
+            s = 0.0
+            for k in sorted(rows[i] & rows[j]):
+                s += a[i, k] * bb[k, j]
+            ref[i, j] = s
+    assert np.abs(ops.masked_product(a, bb, mask) - ref).max() < 1e-14
+    got = native.masked_product_csr(rp, col, a[mask], bb[mask])
+    assert np.array_equal(got, ref[mask])          # same summation order: bit-exact
+
+
+def test_product_c_merge_equals_dense(cfg1_setup):
+    ks, mask, rp, col = cfg1_setup["ks"], cfg1_setup["mask_prior"], cfg1_setup["rp"], cfg1_setup["col"]
+    a = np.where(mask, ks, 0.0)
+    kt = a * (1.0 + 0.1 * _rand_on(mask, 205).clip(0))   # perturbed, non-symmetric operand
+    dense = ops.masked_product(a, kt, mask)
+    got = native.masked_product_csr(rp, col, a[mask], kt[mask])
+    ref = dense[mask]
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_product_identities(cfg1_setup):
+    mask, rp, col = cfg1_setup["mask_prior"], cfg1_setup["rp"], cfg1_setup["col"]
+    a = np.where(mask, cfg1_setup["ks"], 0.0)
+    eye = np.eye(2048)
+    # exact: one nonzero term per entry
+    assert np.array_equal(native.masked_product_csr(rp, col, eye[mask], a[mask]), a[mask])
+    assert np.array_equal(native.masked_product_csr(rp, col, a[mask], eye[mask]), a[mask])
+    d1, d2 = np.diag(np.arange(1.0, 2049.0)), np.diag(np.linspace(-1, 1, 2048))
+    assert np.array_equal(native.masked_product_csr(rp, col, d1[mask], d2[mask]), (d1 @ d2)[mask])
+    # symmetric operands in the same summation order give an exactly symmetric product
+    s = np.triu(a) + np.triu(a, 1).T
+    c = np.zeros_like(s)
+    c[mask] = native.masked_product_csr(rp, col, s[mask], s[mask])
+    assert np.array_equal(c, c.T)
+
+
+def test_product_bilinear_and_full_pattern():
+    t, b, rp, col, mask = _small(n=256)
+    a, bb, cc = _rand_on(mask, 3), _rand_on(mask, 4), _rand_on(mask, 5)
+    lhs = ops.masked_product(2.0 * a + 3.0 * cc, bb, mask)
+    rhs = 2.0 * ops.masked_product(a, bb, mask) + 3.0 * ops.masked_product(cc, bb, mask)
+    assert np.abs(lhs - rhs).max() < 1e-12
+    # eta -> infinity keeps everything: the product is the plain matrix product
+    t, b, rp, col, full = _small(n=256, eta=1e9)
+    assert full.all()
+    a, bb = _rand_on(full, 6), _rand_on(full, 7)
+    got = native.masked_product_csr(rp, col, a[full], bb[full])
+    assert np.allclose(got, (a @ bb)[full], rtol=1e-12, atol=1e-13)
+
+
+def test_axpy_and_identity(cfg1_setup):
+    mask = cfg1_setup["mask_post"]
+    y = np.where(mask, cfg1_setup["ks"], 0.0)
+    out = ops.axpy(0.1, None, 1.0, y, mask)
+    off = ~np.eye(2048, dtype=bool)
+    assert np.array_equal(out[off], y[off])
+    assert np.array_equal(np.diag(out), 0.1 + np.diag(y))
+    z = ops.axpy(2.0, y, -1.0, y, mask)
+    assert np.array_equal(z, np.where(mask, 2.0 * y - y, 0.0))
+
+
+def _spd_problem(n=256, eta=1.0, mu=1e-2, p=2, ell=0.2, d=3, seed=4, leaf=32):
+    t = tree.build_tree(synth.points_cube(n, d, seed), leaf)
+    b = samplets.build_samplets(t, 1)
+    rp, col = pattern.entry_csr(b, pattern.block_pattern(t, eta))
+    mask = pattern.dense_mask(rp, col, n)
+    ks = compress.compress_dense(b, p, ell, 1.0 / n)
+    a = np.where(mask, ks, 0.0) + mu * np.eye(n)
+    return b, mask, a
+
+
+def test_newton_schulz_full_pattern_is_textbook_inverse():
+    b, mask, a = _spd_problem(eta=1e9)
+    assert mask.all()
+    x, res, _ = ops.newton_schulz(a, mask, 20, 2.0 / (1.0 + 2 * 1e-2))
+    assert res[-1] < 1e-12
+    assert np.allclose(x, np.linalg.inv(a), rtol=1e-9, atol=1e-9)
+    assert all(res[k + 1] <= res[k] for k in range(len(res) - 1) if res[k] > 1e-13)
+
+
+def test_newton_schulz_masked_fixed_point():
+    # The fixed point with P_S(A X) = I is given column by column by the local
+    # solves A[S_j, S_j] x = e_j (independent computation via LAPACK).
+    b, mask, a = _spd_problem(n=1024, d=2, leaf=16, eta=1.0)
+    assert mask.mean() < 0.5
+    x, res, _ = ops.newton_schulz(a, mask, 40, 2.0 / (1.0 + 2 * 1e-2))
+    xstar = ops.column_local_inverse(a, mask)
+    assert res[-1] < 1e-10
+    assert np.abs(x - xstar).max() < 1e-8 * np.abs(xstar).max()
+
+
+def test_adjoint_dot_product_identity():
+    t, b, rp, col, mask = _small(n=256)
+    a, bb, dc = _rand_on(mask, 8), _rand_on(mask, 9), _rand_on(mask, 10)
+    da = ops.masked_product(dc, bb.T, mask)      # P_S(dC B^T)
+    db = ops.masked_product(a.T, dc, mask)       # P_S(A^T dC)
+    d_a, d_b = _rand_on(mask, 11), _rand_on(mask, 12)
+    lhs_a = np.sum(dc * ops.masked_product(d_a, bb, mask))
+    lhs_b = np.sum(dc * ops.masked_product(a, d_b, mask))
+    assert abs(lhs_a - np.sum(da * d_a)) < 1e-12 * abs(lhs_a)
+    assert abs(lhs_b - np.sum(db * d_b)) < 1e-12 * abs(lhs_b)
+
+
+def _gp(n, eta, ell, iters=15, mu=1e-2):
+    t = tree.build_tree(synth.points_sphere(n, 5), 32)
+    b = samplets.build_samplets(t, 1)
+    rp, col = pattern.entry_csr(b, pattern.block_pattern(t, eta))
+    mask = pattern.dense_mask(rp, col, n)
+    y = synth.normals(n, 105)
+
+    def amat(l):
+        return np.where(mask, compress.compress_dense(b, 1, l, 1.0 / n), 0.0) + mu * np.eye(n)
+
+    da = np.where(mask, compress.compress_dense(b, 1, ell, 1.0 / n, deriv=True), 0.0)
+    return b, mask, y, amat, da
+
+
+@pytest.mark.parametrize("eta", [1.0, 1e9])
+def test_gp_gradient_matches_central_fd(eta):
+    b, mask, y, amat, da = _gp(256, eta, 0.3)
+    alpha0 = 2.0 / (1.0 + 2e-2)
+    f, g, _ = ops.gp_objective_and_grad(amat(0.3), da, mask, y, 15, alpha0)
+    h = 1e-4
+    fp = ops.quadform(ops.newton_schulz(amat(0.3 + h), mask, 15, alpha0)[0], y)
+    fm = ops.quadform(ops.newton_schulz(amat(0.3 - h), mask, 15, alpha0)[0], y)
+    fd = (fp - fm) / (2 * h)
+    assert abs(g - fd) < 1e-6 * abs(fd)
+
+
+def test_gp_gradient_closed_form_full_pattern():
+    # converged, unmasked: d/dl y^T A^{-1} y = -y^T A^{-1} A' A^{-1} y
+    b, mask, y, amat, da = _gp(256, 1e9, 0.3)
+    a = amat(0.3)
+    f, g, res = ops.gp_objective_and_grad(a, da, mask, y, 30, 2.0 / (1.0 + 2e-2))
+    ai = np.linalg.inv(a)
+    assert res[-1] < 1e-12
+    assert abs(f - y @ ai @ y) < 1e-10 * abs(f)
+    assert abs(g - (-(y @ ai @ da @ ai @ y))) < 1e-9 * abs(g)
+
+
+def test_sampled_rows_product_matches_full(cfg1_setup):
+    mask, rp, col = cfg1_setup["mask_prior"], cfg1_setup["rp"], cfg1_setup["col"]
+    a = np.where(mask, cfg1_setup["ks"], 0.0)
+    full = native.masked_product_csr(rp, col, a[mask], a[mask])
+    rows = np.array([0, 5, 64, 900, 2047])
+    part, cnt = native.masked_product_rows(rows, rp, col, a[mask], a[mask])
+    assert cnt == sum(rp[r + 1] - rp[r] for r in rows)
+    for r in rows:
+        assert np.array_equal(part[rp[r]:rp[r + 1]], full[rp[r]:rp[r + 1]])
