@@ -1,0 +1,202 @@
+/*
+ * spm.h -- samplet (S-format) kernel matrix arithmetic on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libspm.  Plain pointers and sizes only.  "host" arguments are read
+ * (or written) before the call returns; "device" arguments are device memory
+ * allocated by the caller (for instance torch tensors) and are accessed
+ * asynchronously on the HIP stream passed as `stream` (NULL = the null stream).
+ * Every function returns an spm_status; nothing aborts and no exception crosses
+ * the boundary.  spm_last_error() gives a message for the last failure on the
+ * calling thread.  Asynchronous kernel faults surface at the caller's next
+ * synchronising call.
+ *
+ * Terms (Harbrecht, Multerer, Schenk, Schwab, "Multiresolution kernel matrix
+ * algebra", Sections 3 and 4):
+ *   cluster tree  binary tree of point clusters (Section 3.2, Definition of a
+ *                 cluster tree); clusters are numbered level by level.
+ *   basis         samplet basis (Section 3.2, eq. (Wbasis)): the root's scaling
+ *                 distributions followed by every cluster's samplets.  Cluster c
+ *                 owns the basis indices [cluster_start[c], cluster_start[c+1]).
+ *   pattern S     compression pattern: the basis pairs whose clusters are not
+ *                 eta-admissible (Section 3.3, eq. (cutoff)), optionally thinned
+ *                 entry by entry (a-posteriori pattern, Section 5).  S must be
+ *                 structurally symmetric and contain the diagonal.
+ *   S-matrix      values on S stored in the library's tile layout: for every
+ *                 block-row (cluster) c, the tiles (c, c') for c' in S_c in
+ *                 ascending c', each a dense n_c x n_c' block stored
+ *                 column-major (element (i, j) at j*n_c + i).  Length n_stored.
+ *                 Positions that are inside a tile but outside S hold 0.
+ *
+ * Precision modes for value arrays:
+ *   SPM_F64       double[n_stored]
+ *   SPM_F32SPLIT  float hi[n_stored] followed by float lo[n_stored]
+ *                 (x = hi + lo, hi = fl32(x), lo = fl32(x - hi)); arithmetic in
+ *                 FP32 with error-free products and compensated sums.
+ *   SPM_F32ACC    float hi[n_stored]; FP32 products, compensated FP32 sums.
+ */
+#ifndef SPM_H
+#define SPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPM_OK = 0,
+    SPM_EINVAL = -1,        /* bad argument: null pointer, size, aliasing, flag */
+    SPM_EPATTERN = -2,      /* pattern fails validation */
+    SPM_ENOMEM = -3,        /* host or device allocation failed */
+    SPM_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
+    SPM_ENOTCONV = -5,      /* Newton-Schulz residual non-finite or not decreasing */
+    SPM_EUNSUPPORTED = -6   /* valid input outside what the kernels support */
+} spm_status;
+
+typedef enum { SPM_F64 = 0, SPM_F32SPLIT = 1, SPM_F32ACC = 2 } spm_prec;
+
+typedef struct spm_tree_s *spm_tree;        /* host-side cluster tree + samplet basis */
+typedef struct spm_pattern_s *spm_pattern;  /* device-side tiled pattern; immutable */
+
+const char *spm_status_string(int status);
+const char *spm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Construction (host).  Section 3.2: cluster tree and two-scale samplet
+ * construction; Section 3.3: eta-admissibility pattern.
+ * ---------------------------------------------------------------------- */
+
+/* Cluster tree of n points (host, row-major n x d, 1 <= d <= 3, mutually
+ * distinct) by median splits along the longest bounding-box side until a
+ * cluster has at most leaf_size points; samplets with vanishing moments up to
+ * total degree q (Section 3.2, eqs. (QR), (vanishingMomentsQR)).  The handle
+ * owns copies of everything it needs.  EINVAL for bad sizes; EUNSUPPORTED if a
+ * cluster would own more than 32 basis functions (the kernels' tile limit). */
+int spm_tree_build(const double *points, int64_t n, int32_t d, int32_t leaf_size, int32_t q,
+                   spm_tree *out);
+int spm_tree_destroy(spm_tree t);
+
+/* n_clusters, depth (max level), m = number of monomials of degree <= q. */
+int spm_tree_info(spm_tree t, int32_t *n_clusters, int32_t *depth, int32_t *m);
+
+/* Host output arrays (any may be NULL): perm[n] (original index of the k-th
+ * point in tree order), cluster_start[nc+1] (basis ranges), level[nc],
+ * pt_start[nc], pt_size[nc] (point ranges in tree order). */
+int spm_tree_arrays(spm_tree t, int64_t *perm, int64_t *cluster_start, int32_t *level,
+                    int64_t *pt_start, int64_t *pt_size);
+
+/* Block pattern of the eta-admissibility condition (Section 3.3, eq. (cutoff)):
+ * cluster pairs (c, c') with dist(B_c, B_c') < eta * max(diam B_c, diam B_c'),
+ * bounding boxes B, Euclidean diameter and gap distance.  Host outputs:
+ * blk_row_ptr[nc+1]; blk_col[n_blocks] sorted per row (pass blk_col = NULL to
+ * get n_blocks first). */
+int spm_tree_block_pattern(spm_tree t, double eta, int64_t *blk_row_ptr, int32_t *blk_col,
+                           int64_t *n_blocks);
+
+/* ------------------------------------------------------------------------
+ * Pattern upload: validation, tile layout, transpose map, schedule.
+ * ---------------------------------------------------------------------- */
+
+/* Entry-level pattern (host CSR, row_ptr[n+1] int64, col_idx sorted unique per
+ * row) with cluster ranges cluster_start[n_clusters+1] (host, level order).
+ * Tiles are the cluster pairs holding at least one entry; positions of a tile
+ * outside S are masked.  EPATTERN if unsorted, duplicate, out of range,
+ * unsymmetric, missing a diagonal entry, or cluster ranges do not tile [0, n). */
+int spm_compress_pattern_upload(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                                int32_t n_clusters, const int64_t *cluster_start, void *stream,
+                                spm_pattern *out);
+
+/* Block pattern (host cluster-level CSR as from spm_tree_block_pattern); every
+ * tile is full.  Same validation at cluster level. */
+int spm_block_pattern_upload(int64_t n, int32_t n_clusters, const int64_t *cluster_start,
+                             const int64_t *blk_row_ptr, const int32_t *blk_col, void *stream,
+                             spm_pattern *out);
+
+int spm_pattern_destroy(spm_pattern p);
+
+/* nnz = |S|, n_stored = value-array length, n_tiles, macs = exact multiply-adds
+ * of one product P_S(A B) over the tile structure (sum over output tiles (c,c')
+ * of n_c n_c' sum_{mu in S_c cap S_c'} n_mu). */
+int spm_pattern_info(spm_pattern p, int64_t *nnz, int64_t *n_stored, int64_t *n_tiles, double *macs);
+
+/* Host copies of the tile structure (any may be NULL): tile_row[n_tiles],
+ * tile_col[n_tiles], tile_off[n_tiles] (element offset of each tile). */
+int spm_pattern_tiles(spm_pattern p, int32_t *tile_row, int32_t *tile_col, int64_t *tile_off);
+
+/* Entry-level CSR of S (host outputs, row_ptr[n+1], col_idx[nnz]). */
+int spm_pattern_download_csr(spm_pattern p, int64_t *row_ptr, int32_t *col_idx);
+
+/* Device conversions between CSR order (values of S row by row, nnz doubles)
+ * and the tile layout (n_stored doubles; masked positions set to 0). */
+int spm_values_from_csr(spm_pattern p, const double *csr_vals, double *vals, void *stream);
+int spm_values_to_csr(spm_pattern p, const double *vals, double *csr_vals, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Compression on the device (Section 3.3): vals = P_S(T K T^T) with
+ * K = scale * [k(|x_i - x_j|)] the Matern kernel nu = matern_p + 1/2 of
+ * lengthscale ell (deriv = 1: its derivative in ell) at the tree's points.
+ * The pattern must have been built on the same tree's cluster ranges.
+ * Exact O(N^2) evaluation by a two-sided fast samplet transform in panels;
+ * temporary device memory is allocated and freed inside.
+ * ---------------------------------------------------------------------- */
+int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t matern_p, double ell, double scale,
+                        int32_t deriv, double *vals, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Arithmetic on S-matrices (device value arrays of one pattern).
+ * ---------------------------------------------------------------------- */
+
+/* C = P_S(op(A) op(B)), op(X) = X or X^T (Section 4.1, Theorem (product),
+ * eq. (product)): for every (i,j) in S, c_ij = sum_k op(A)_ik op(B)_kj, the sum
+ * over the k with (i,k) and (k,j) in S, exact on the pattern.  A, B, C in
+ * precision `prec`; C must not alias A or B (EINVAL). */
+int spm_masked_gemm(spm_pattern p, int prec, const void *A, int transA, const void *B, int transB,
+                    void *C, void *stream);
+
+/* Adjoint of C = P_S(A B) (one pattern for all operands):
+ * dA = P_S(dC B^T), dB = P_S(A^T dC).  dA or dB may be NULL to skip it. */
+int spm_masked_gemm_backward(spm_pattern p, int prec, const void *dC, const void *A, const void *B,
+                             void *dA, void *dB, void *stream);
+
+/* Y = alpha X + beta Y on the stored values (formatted addition, Section 4.1);
+ * X = NULL stands for the identity (only the diagonal of Y changes). */
+int spm_axpy(spm_pattern p, int prec, double alpha, const void *X, double beta, void *Y, void *stream);
+
+/* Precision conversion between value arrays (F64 -> split rounds to nearest;
+ * split -> F64 is exact). */
+int spm_convert(spm_pattern p, int prec_from, const void *X, int prec_to, void *Y, void *stream);
+
+/* Deterministic FP64 reductions (fixed order, no atomics); result written to
+ * the device double *out.
+ *   spm_sqdist      sum_e (x_e - y_e)^2 over stored values (Y = NULL: sum x_e^2)
+ *   spm_sqdist_eye  || alpha I - X ||_F^2 over S
+ *   spm_dot         <X, Y>_S = sum_e x_e y_e
+ *   spm_quadform    y^T X y, y a device vector of length n in basis order  */
+int spm_sqdist(spm_pattern p, int prec, const void *X, const void *Y, double *out, void *stream);
+int spm_sqdist_eye(spm_pattern p, int prec, double alpha, const void *X, double *out, void *stream);
+int spm_dot(spm_pattern p, const double *X, const double *Y, double *out, void *stream);
+int spm_quadform(spm_pattern p, const double *X, const double *y, double *out, void *stream);
+
+/* X = alpha P_S(y y^T) (the seed of the quadratic-form adjoint). */
+int spm_fill_outer(spm_pattern p, double alpha, const double *y, double *X, void *stream);
+
+/* Masked Newton-Schulz inverse of A (FP64 on S):
+ *   X_0 = alpha0 I;  for k = 0..iters-1:  Y_k = P_S(A X_k),  r_k = ||I - Y_k||_F / sqrt(n),
+ *   Z_k = 2I - Y_k,  X_{k+1} = P_S(X_k Z_k);  finally r_iters = ||I - P_S(A X_iters)||_F / sqrt(n).
+ * Iterations 0 .. iters-n_final_f64-1 run in precision `bulk`, the rest and
+ * every residual in FP64.  X (device, F64) receives X_iters.  residuals (device,
+ * iters+1 doubles).  checkpoints (host array of iters+1 device F64 pointers, or
+ * NULL) receives X_0 .. X_iters.  scratch: device workspace of at least
+ * spm_newton_schulz_scratch() bytes.  Returns ENOTCONV when the final residual
+ * is not finite (X is still written); this is the only call that synchronises
+ * the stream (to read the final residual). */
+int spm_newton_schulz_scratch(spm_pattern p, int bulk, size_t *bytes);
+int spm_newton_schulz(spm_pattern p, const double *A, double *X, int32_t iters, int32_t n_final_f64,
+                      int bulk, double alpha0, double *residuals, double *const *checkpoints,
+                      void *scratch, size_t scratch_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPM_H */

@@ -1,0 +1,628 @@
+// Host side of libspm: cluster tree, samplet two-scale transforms, eta-admissibility
+// block pattern, pattern validation and the tiled layout.
+//
+// Built with -ffp-contract=off: the admissibility test and the tree split compare
+// floating-point values, and every operation there rounds on its own.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <thread>
+
+#include "spm_internal.h"
+
+namespace spm {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+}  // namespace spm
+
+using spm::fail;
+
+extern "C" const char *spm_status_string(int s)
+{
+    switch (s) {
+    case SPM_OK: return "ok";
+    case SPM_EINVAL: return "invalid argument";
+    case SPM_EPATTERN: return "invalid pattern";
+    case SPM_ENOMEM: return "out of memory";
+    case SPM_EHIP: return "HIP error";
+    case SPM_ENOTCONV: return "not converged";
+    case SPM_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *spm_last_error(void) { return spm::g_last_error.c_str(); }
+
+// ----------------------------------------------------------------------------------
+// Cluster tree and samplets (Section 3.2)
+// ----------------------------------------------------------------------------------
+namespace {
+
+// Exponents of all monomials of total degree <= q in d variables: degree by degree,
+// inside a degree in descending lexicographic order of the exponent tuple.
+std::vector<std::vector<int>> monomials(int d, int q)
+{
+    std::vector<std::vector<int>> out;
+    for (int deg = 0; deg <= q; ++deg) {
+        std::vector<std::vector<int>> same;
+        std::vector<int> e(d, 0);
+        // enumerate all tuples with entries 0..deg, keep those summing to deg
+        int total = 1;
+        for (int a = 0; a < d; ++a) total *= (deg + 1);
+        for (int code = 0; code < total; ++code) {
+            int c = code, s = 0;
+            for (int a = d - 1; a >= 0; --a) { e[a] = c % (deg + 1); c /= (deg + 1); s += e[a]; }
+            if (s == deg) same.push_back(e);
+        }
+        std::sort(same.begin(), same.end(), std::greater<std::vector<int>>());
+        out.insert(out.end(), same.begin(), same.end());
+    }
+    return out;
+}
+
+// In-place Householder QR of the column-major (n x m) matrix r, n > m; q (n x n,
+// column-major) receives H_1 ... H_m.  Reflector of column k maps x = r[k:, k] to
+// alpha e_1 with alpha = -sign(x_0) ||x|| (sign(0) = +1); zero columns are skipped.
+void householder(int n, int m, double *r, double *q)
+{
+    std::fill(q, q + (size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) q[(size_t)i * n + i] = 1.0;
+    std::vector<double> v(n);
+    for (int k = 0; k < m; ++k) {
+        double *x = r + (size_t)k * n;
+        double ss = 0.0;
+        for (int i = k; i < n; ++i) ss += x[i] * x[i];
+        double nrm = std::sqrt(ss);
+        if (nrm == 0.0) continue;
+        double alpha = x[k] >= 0.0 ? -nrm : nrm;
+        for (int i = k; i < n; ++i) v[i] = x[i];
+        v[k] -= alpha;
+        double vv = 0.0;
+        for (int i = k; i < n; ++i) vv += v[i] * v[i];
+        double beta = 2.0 / vv;
+        for (int j = k; j < m; ++j) {             // R <- H R
+            double *col = r + (size_t)j * n;
+            double t = 0.0;
+            for (int i = k; i < n; ++i) t += v[i] * col[i];
+            t *= beta;
+            for (int i = k; i < n; ++i) col[i] -= t * v[i];
+        }
+        for (int row = 0; row < n; ++row) {       // Q <- Q H
+            double t = 0.0;
+            for (int i = k; i < n; ++i) t += q[(size_t)i * n + row] * v[i];
+            t *= beta;
+            for (int i = k; i < n; ++i) q[(size_t)i * n + row] -= t * v[i];
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int spm_tree_build(const double *points, int64_t n, int32_t d, int32_t leaf, int32_t q,
+                              spm_tree *out)
+{
+    if (!points || !out) return fail(SPM_EINVAL, "spm_tree_build: null pointer");
+    if (n < 1 || d < 1 || d > 3 || leaf < 1 || q < 0 || q > 8 || n > INT32_MAX)
+        return fail(SPM_EINVAL, "spm_tree_build: bad size argument");
+    *out = nullptr;
+    spm_tree_s *t = new (std::nothrow) spm_tree_s;
+    if (!t) return fail(SPM_ENOMEM, "spm_tree_build: host allocation");
+    try {
+        t->n = n; t->d = d; t->leaf = leaf; t->q = q;
+        auto mons = monomials(d, q);
+        const int m = (int)mons.size();
+        t->m = m;
+        std::vector<int64_t> perm(n);
+        for (int64_t i = 0; i < n; ++i) perm[i] = i;
+        auto X = [&](int64_t i, int a) { return points[i * d + a]; };
+
+        // breadth-first splitting; clusters are appended level by level
+        auto add = [&](int64_t s, int64_t sz, int lev, int par) {
+            t->pstart.push_back(s); t->psize.push_back(sz); t->level.push_back(lev);
+            t->parent.push_back(par); t->son0.push_back(-1); t->son1.push_back(-1);
+            for (int a = 0; a < d; ++a) {
+                double lo = X(perm[s], a), hi = lo;
+                for (int64_t k = s + 1; k < s + sz; ++k) { lo = std::min(lo, X(perm[k], a)); hi = std::max(hi, X(perm[k], a)); }
+                t->lo.push_back(lo); t->hi.push_back(hi);
+            }
+            return (int)t->pstart.size() - 1;
+        };
+        add(0, n, 0, -1);
+        for (size_t c = 0; c < t->pstart.size(); ++c) {
+            int64_t s = t->pstart[c], sz = t->psize[c];
+            if (sz <= leaf) continue;
+            int axis = 0;
+            double best = t->hi[c * d] - t->lo[c * d];
+            for (int a = 1; a < d; ++a) {
+                double e = t->hi[c * d + a] - t->lo[c * d + a];
+                if (e > best) { best = e; axis = a; }
+            }
+            std::sort(perm.begin() + s, perm.begin() + s + sz, [&](int64_t a, int64_t b) {
+                double xa = X(a, axis), xb = X(b, axis);
+                return xa < xb || (xa == xb && a < b);
+            });
+            int64_t h = sz / 2;
+            int lev = t->level[c] + 1;
+            int a0 = add(s, h, lev, (int)c);
+            int a1 = add(s + h, sz - h, lev, (int)c);
+            t->son0[c] = a0; t->son1[c] = a1;
+        }
+        const int nc = (int)t->pstart.size();
+        t->nc = nc;
+        t->depth = *std::max_element(t->level.begin(), t->level.end());
+        t->perm = perm;
+        t->pts.resize((size_t)n * d);
+        for (int64_t k = 0; k < n; ++k)
+            for (int a = 0; a < d; ++a) t->pts[k * d + a] = X(perm[k], a);
+
+        // two-scale transforms, leaves first (sons are numbered after their father)
+        t->nin.assign(nc, 0); t->nscal.assign(nc, 0);
+        t->qoff.assign(nc + 1, 0); t->slotoff.assign(nc + 1, 0);
+        std::vector<std::vector<double>> scal(nc);        // (size x nscal) column-major coefficients
+        std::vector<std::vector<int64_t>> slots(nc);
+        std::vector<std::vector<double>> qs(nc);
+        for (int c = nc - 1; c >= 0; --c) {
+            const int64_t s = t->pstart[c], sz = t->psize[c];
+            std::vector<double> phi;      // (sz x nin) column-major
+            std::vector<int64_t> sl;
+            int nin;
+            if (t->son0[c] < 0) {
+                nin = (int)sz;
+                phi.assign((size_t)sz * nin, 0.0);
+                for (int k = 0; k < nin; ++k) { phi[(size_t)k * sz + k] = 1.0; sl.push_back(s + k); }
+            } else {
+                int a = t->son0[c], b = t->son1[c];
+                int na = t->nscal[a], nb = t->nscal[b];
+                int64_t sa = t->psize[a], sb = t->psize[b];
+                nin = na + nb;
+                phi.assign((size_t)sz * nin, 0.0);
+                for (int k = 0; k < na; ++k)
+                    std::memcpy(&phi[(size_t)k * sz], &scal[a][(size_t)k * sa], sa * sizeof(double));
+                for (int k = 0; k < nb; ++k)
+                    std::memcpy(&phi[(size_t)(na + k) * sz + sa], &scal[b][(size_t)k * sb], sb * sizeof(double));
+                sl.insert(sl.end(), slots[a].begin(), slots[a].begin() + na);
+                sl.insert(sl.end(), slots[b].begin(), slots[b].begin() + nb);
+                std::vector<double>().swap(scal[a]);
+                std::vector<double>().swap(scal[b]);
+            }
+            t->nin[c] = nin;
+            std::vector<double> qm((size_t)nin * nin, 0.0);
+            if (nin <= m) {
+                for (int k = 0; k < nin; ++k) qm[(size_t)k * nin + k] = 1.0;
+                t->nscal[c] = nin;
+                scal[c] = phi;
+            } else {
+                // moment matrix transposed: mt[k][alpha] = sum_p phi_k(p) mono_alpha(p), (nin x m) column-major
+                double ctr[3], half = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    ctr[a] = 0.5 * (t->lo[c * d + a] + t->hi[c * d + a]);
+                    half = std::max(half, 0.5 * (t->hi[c * d + a] - t->lo[c * d + a]));
+                }
+                if (half == 0.0) half = 1.0;
+                std::vector<double> vmono((size_t)sz * m);
+                for (int64_t p = 0; p < sz; ++p) {
+                    double y[3];
+                    for (int a = 0; a < d; ++a) y[a] = (t->pts[(s + p) * d + a] - ctr[a]) / half;
+                    for (int al = 0; al < m; ++al) {
+                        double v = 1.0;
+                        for (int a = 0; a < d; ++a)
+                            for (int e = 0; e < mons[al][a]; ++e) v *= y[a];
+                        vmono[(size_t)al * sz + p] = v;
+                    }
+                }
+                std::vector<double> mt((size_t)nin * m, 0.0);
+                for (int al = 0; al < m; ++al)
+                    for (int k = 0; k < nin; ++k) {
+                        double acc = 0.0;
+                        const double *f = &phi[(size_t)k * sz];
+                        const double *v = &vmono[(size_t)al * sz];
+                        for (int64_t p = 0; p < sz; ++p) acc += f[p] * v[p];
+                        mt[(size_t)al * nin + k] = acc;
+                    }
+                householder(nin, m, mt.data(), qm.data());
+                t->nscal[c] = m;
+                scal[c].assign((size_t)sz * m, 0.0);           // phi Q[:, :m]
+                for (int j = 0; j < m; ++j)
+                    for (int k = 0; k < nin; ++k) {
+                        double w = qm[(size_t)j * nin + k];
+                        if (w == 0.0) continue;
+                        const double *f = &phi[(size_t)k * sz];
+                        double *o = &scal[c][(size_t)j * sz];
+                        for (int64_t p = 0; p < sz; ++p) o[p] += w * f[p];
+                    }
+            }
+            qs[c] = std::move(qm);
+            slots[c] = std::move(sl);
+        }
+        // flatten transforms; basis ranges
+        t->cstart.assign(nc + 1, 0);
+        for (int c = 0; c < nc; ++c) {
+            t->qoff[c + 1] = t->qoff[c] + (int64_t)t->nin[c] * t->nin[c];
+            t->slotoff[c + 1] = t->slotoff[c] + t->nin[c];
+            int64_t cnt = (c == 0) ? t->nin[0] : (t->nin[c] - t->nscal[c]);
+            t->cstart[c + 1] = t->cstart[c] + cnt;
+        }
+        if (t->cstart[nc] != n) { delete t; return fail(SPM_EINVAL, "spm_tree_build: basis size mismatch"); }
+        t->qmat.resize(t->qoff[nc]);
+        t->slots.resize(t->slotoff[nc]);
+        for (int c = 0; c < nc; ++c) {
+            std::copy(qs[c].begin(), qs[c].end(), t->qmat.begin() + t->qoff[c]);
+            std::copy(slots[c].begin(), slots[c].end(), t->slots.begin() + t->slotoff[c]);
+            if (t->cstart[c + 1] - t->cstart[c] > spm::kMaxFun) {
+                delete t;
+                return fail(SPM_EUNSUPPORTED, "spm_tree_build: a cluster owns more than 32 basis functions");
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        delete t;
+        return fail(SPM_ENOMEM, "spm_tree_build: host allocation");
+    }
+    *out = t;
+    return SPM_OK;
+}
+
+extern "C" int spm_tree_destroy(spm_tree t)
+{
+    delete t;
+    return SPM_OK;
+}
+
+extern "C" int spm_tree_info(spm_tree t, int32_t *nc, int32_t *depth, int32_t *m)
+{
+    if (!t) return fail(SPM_EINVAL, "spm_tree_info: null tree");
+    if (nc) *nc = t->nc;
+    if (depth) *depth = t->depth;
+    if (m) *m = t->m;
+    return SPM_OK;
+}
+
+extern "C" int spm_tree_arrays(spm_tree t, int64_t *perm, int64_t *cstart, int32_t *level,
+                               int64_t *pstart, int64_t *psize)
+{
+    if (!t) return fail(SPM_EINVAL, "spm_tree_arrays: null tree");
+    if (perm) std::copy(t->perm.begin(), t->perm.end(), perm);
+    if (cstart) std::copy(t->cstart.begin(), t->cstart.end(), cstart);
+    if (level) std::copy(t->level.begin(), t->level.end(), level);
+    if (pstart) std::copy(t->pstart.begin(), t->pstart.end(), pstart);
+    if (psize) std::copy(t->psize.begin(), t->psize.end(), psize);
+    return SPM_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// eta-admissibility (Section 3.3, eq. (cutoff)) by pruned descent of the tree:
+// admissibility of (c, c') is inherited by the sons of c' (their boxes lie inside
+// B_c', so the gap can only grow and the diameter only shrink).
+// ----------------------------------------------------------------------------------
+extern "C" int spm_tree_block_pattern(spm_tree t, double eta, int64_t *rp, int32_t *col, int64_t *nblocks)
+{
+    if (!t || !rp || !nblocks) return fail(SPM_EINVAL, "spm_tree_block_pattern: null pointer");
+    if (!(eta > 0.0)) return fail(SPM_EINVAL, "spm_tree_block_pattern: eta must be positive");
+    const int nc = t->nc, d = t->d;
+    std::vector<double> diam(nc);
+    for (int c = 0; c < nc; ++c) {
+        double acc = 0.0;
+        for (int a = 0; a < d; ++a) {
+            double e = t->hi[c * d + a] - t->lo[c * d + a];
+            acc = acc + e * e;
+        }
+        diam[c] = std::sqrt(acc);
+    }
+    auto keep = [&](int c, int c2) {
+        double acc = 0.0;
+        for (int a = 0; a < d; ++a) {
+            double g = std::max(0.0, std::max(t->lo[c2 * d + a] - t->hi[c * d + a], t->lo[c * d + a] - t->hi[c2 * d + a]));
+            acc = acc + g * g;
+        }
+        double dist = std::sqrt(acc);
+        double bound = eta * std::max(diam[c], diam[c2]);
+        return dist < bound;
+    };
+    std::vector<std::vector<int32_t>> rows(nc);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nth; ++w)
+        th.emplace_back([&, w]() {
+            std::vector<int32_t> stack;
+            for (int c = (int)w; c < nc; c += (int)nth) {
+                auto &r = rows[c];
+                stack.assign(1, 0);
+                while (!stack.empty()) {
+                    int c2 = stack.back();
+                    stack.pop_back();
+                    if (!keep(c, c2)) continue;
+                    r.push_back(c2);
+                    if (t->son0[c2] >= 0) { stack.push_back(t->son1[c2]); stack.push_back(t->son0[c2]); }
+                }
+                std::sort(r.begin(), r.end());
+            }
+        });
+    for (auto &x : th) x.join();
+    rp[0] = 0;
+    for (int c = 0; c < nc; ++c) rp[c + 1] = rp[c] + (int64_t)rows[c].size();
+    *nblocks = rp[nc];
+    if (col)
+        for (int c = 0; c < nc; ++c) std::copy(rows[c].begin(), rows[c].end(), col + rp[c]);
+    return SPM_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// Pattern validation and tiled layout
+// ----------------------------------------------------------------------------------
+namespace {
+
+int check_clusters(int64_t n, int32_t nc, const int64_t *cs)
+{
+    if (nc < 1) return fail(SPM_EPATTERN, "cluster count must be positive");
+    if (cs[0] != 0 || cs[nc] != n) return fail(SPM_EPATTERN, "cluster ranges do not tile [0, n)");
+    for (int32_t c = 0; c < nc; ++c) {
+        if (cs[c + 1] < cs[c]) return fail(SPM_EPATTERN, "cluster ranges decrease");
+        if (cs[c + 1] - cs[c] > spm::kMaxFun)
+            return fail(SPM_EUNSUPPORTED, "a cluster owns more than 32 basis functions");
+    }
+    return SPM_OK;
+}
+
+// Sorted unique columns per row, all in [0, ncols).
+int check_csr(int64_t nrows, int64_t ncols, const int64_t *rp, const int32_t *col, const char *what)
+{
+    if (rp[0] != 0) return fail(SPM_EPATTERN, std::string(what) + ": row_ptr[0] != 0");
+    for (int64_t i = 0; i < nrows; ++i) {
+        if (rp[i + 1] < rp[i]) return fail(SPM_EPATTERN, std::string(what) + ": row_ptr decreases");
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= ncols) return fail(SPM_EPATTERN, std::string(what) + ": column out of range");
+            if (e > rp[i] && col[e] <= col[e - 1])
+                return fail(SPM_EPATTERN, std::string(what) + ": columns not sorted and unique");
+        }
+    }
+    return SPM_OK;
+}
+
+bool has(const int64_t *rp, const int32_t *col, int64_t i, int32_t j)
+{
+    return std::binary_search(col + rp[i], col + rp[i + 1], j);
+}
+
+int check_symmetric_diag(int64_t nrows, const int64_t *rp, const int32_t *col, const std::vector<int32_t> *need_diag,
+                         const char *what)
+{
+    for (int64_t i = 0; i < nrows; ++i) {
+        bool want = need_diag ? (*need_diag)[i] > 0 : true;
+        if (want && !has(rp, col, i, (int32_t)i)) return fail(SPM_EPATTERN, std::string(what) + ": diagonal entry missing");
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (!has(rp, col, col[e], (int32_t)i)) return fail(SPM_EPATTERN, std::string(what) + ": pattern not symmetric");
+    }
+    return SPM_OK;
+}
+
+// Fill the layout of p from its block CSR (p->blk_rp, p->tile_col, p->nfun set).
+void build_layout(spm_pattern_s *p)
+{
+    const int nc = p->nc;
+    const int64_t nt = p->blk_rp[nc];
+    p->n_tiles = nt;
+    p->tile_row.resize(nt);
+    p->tile_off.resize(nt + 1);
+    p->trans.resize(nt);
+    p->colprefix.resize(nt);
+    p->rowbase.resize(nc);
+    p->rowlen.resize(nc);
+    p->diag_tile.assign(nc, -1);
+    p->tile_off[0] = 0;
+    int64_t base = 0;
+    p->max_rowlen = 0;
+    for (int r = 0; r < nc; ++r) {
+        int64_t len = 0;
+        p->max_rowlen = std::max<int32_t>(p->max_rowlen, (int32_t)(p->blk_rp[r + 1] - p->blk_rp[r]));
+        for (int64_t t = p->blk_rp[r]; t < p->blk_rp[r + 1]; ++t) {
+            int c = p->tile_col[t];
+            p->tile_row[t] = r;
+            p->colprefix[t] = len;
+            len += p->nfun[c];
+            p->tile_off[t + 1] = p->tile_off[t] + (int64_t)p->nfun[r] * p->nfun[c];
+            if (c == r) p->diag_tile[r] = (int32_t)t;
+            const int32_t *b = p->tile_col.data() + p->blk_rp[c];
+            const int32_t *e = p->tile_col.data() + p->blk_rp[c + 1];
+            p->trans[t] = (int32_t)(p->blk_rp[c] + (std::lower_bound(b, e, r) - b));
+        }
+        p->rowlen[r] = len;
+        p->rowbase[r] = base;
+        base += len * p->nfun[r];
+    }
+    p->n_stored = p->tile_off[nt];
+    // exact multiply-adds of one product: merge of the two sorted block rows per tile
+    std::vector<double> part(16, 0.0);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nth; ++w)
+        th.emplace_back([&, w]() {
+            double acc = 0.0;
+            for (int64_t t = w; t < nt; t += nth) {
+                int r = p->tile_row[t], c = p->tile_col[t];
+                const int32_t *a = p->tile_col.data() + p->blk_rp[r], *ae = p->tile_col.data() + p->blk_rp[r + 1];
+                const int32_t *b = p->tile_col.data() + p->blk_rp[c], *be = p->tile_col.data() + p->blk_rp[c + 1];
+                int64_t k = 0;
+                while (a < ae && b < be) {
+                    if (*a < *b) ++a;
+                    else if (*b < *a) ++b;
+                    else { k += p->nfun[*a]; ++a; ++b; }
+                }
+                acc += (double)p->nfun[r] * p->nfun[c] * (double)k;
+            }
+            part[w] = acc;
+        });
+    for (auto &x : th) x.join();
+    p->macs = 0.0;
+    for (unsigned w = 0; w < nth; ++w) p->macs += part[w];
+    // schedule: tiles in storage order (one workgroup per output tile)
+    p->order.resize(nt);
+    for (int64_t t = 0; t < nt; ++t) p->order[t] = (int32_t)t;
+}
+
+}  // namespace
+
+extern "C" int spm_block_pattern_upload(int64_t n, int32_t nc, const int64_t *cs, const int64_t *brp,
+                                        const int32_t *bcol, void *stream, spm_pattern *out)
+{
+    if (!cs || !brp || !bcol || !out) return fail(SPM_EINVAL, "spm_block_pattern_upload: null pointer");
+    if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_block_pattern_upload: bad n");
+    *out = nullptr;
+    int st = check_clusters(n, nc, cs);
+    if (st) return st;
+    if ((st = check_csr(nc, nc, brp, bcol, "block pattern"))) return st;
+    std::vector<int32_t> nf(nc);
+    for (int c = 0; c < nc; ++c) nf[c] = (int32_t)(cs[c + 1] - cs[c]);
+    if ((st = check_symmetric_diag(nc, brp, bcol, &nf, "block pattern"))) return st;
+    if (brp[nc] > INT32_MAX) return fail(SPM_EUNSUPPORTED, "more than 2^31-1 tiles");
+    spm_pattern_s *p = new (std::nothrow) spm_pattern_s;
+    if (!p) return fail(SPM_ENOMEM, "host allocation");
+    try {
+        p->n = n; p->nc = nc;
+        p->cstart.assign(cs, cs + nc + 1);
+        p->nfun = nf;
+        // drop tiles of clusters without basis functions
+        p->blk_rp.assign(nc + 1, 0);
+        for (int r = 0; r < nc; ++r) {
+            if (nf[r] > 0)
+                for (int64_t e = brp[r]; e < brp[r + 1]; ++e)
+                    if (nf[bcol[e]] > 0) p->tile_col.push_back(bcol[e]);
+            p->blk_rp[r + 1] = (int64_t)p->tile_col.size();
+        }
+        build_layout(p);
+        p->nnz = p->n_stored;
+        p->masked = false;
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(SPM_ENOMEM, "host allocation");
+    }
+    if ((st = spm::upload_pattern_device(p, (hipStream_t)stream))) {
+        spm::free_pattern_device(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return SPM_OK;
+}
+
+extern "C" int spm_compress_pattern_upload(int64_t n, const int64_t *rp, const int32_t *col, int32_t nc,
+                                           const int64_t *cs, void *stream, spm_pattern *out)
+{
+    if (!rp || !col || !cs || !out) return fail(SPM_EINVAL, "spm_compress_pattern_upload: null pointer");
+    if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_compress_pattern_upload: bad n");
+    *out = nullptr;
+    int st = check_clusters(n, nc, cs);
+    if (st) return st;
+    if ((st = check_csr(n, n, rp, col, "pattern"))) return st;
+    if ((st = check_symmetric_diag(n, rp, col, nullptr, "pattern"))) return st;
+    spm_pattern_s *p = new (std::nothrow) spm_pattern_s;
+    if (!p) return fail(SPM_ENOMEM, "host allocation");
+    try {
+        p->n = n; p->nc = nc;
+        p->cstart.assign(cs, cs + nc + 1);
+        p->nfun.resize(nc);
+        for (int c = 0; c < nc; ++c) p->nfun[c] = (int32_t)(cs[c + 1] - cs[c]);
+        std::vector<int32_t> clus(n);
+        for (int c = 0; c < nc; ++c)
+            for (int64_t i = cs[c]; i < cs[c + 1]; ++i) clus[i] = c;
+        // tiles: cluster pairs holding at least one entry
+        p->blk_rp.assign(nc + 1, 0);
+        std::vector<int32_t> mark(nc, -1);
+        for (int r = 0; r < nc; ++r) {
+            std::vector<int32_t> cols;
+            for (int64_t i = cs[r]; i < cs[r + 1]; ++i)
+                for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+                    int c = clus[col[e]];
+                    if (mark[c] != r) { mark[c] = r; cols.push_back(c); }
+                }
+            std::sort(cols.begin(), cols.end());
+            p->tile_col.insert(p->tile_col.end(), cols.begin(), cols.end());
+            p->blk_rp[r + 1] = (int64_t)p->tile_col.size();
+        }
+        if (p->blk_rp[nc] > INT32_MAX) { delete p; return fail(SPM_EUNSUPPORTED, "more than 2^31-1 tiles"); }
+        build_layout(p);
+        p->nnz = rp[n];
+        p->csr_rp.assign(rp, rp + n + 1);
+        p->csr_col.assign(col, col + rp[n]);
+        p->csr_pos.assign(p->n_stored, -1);
+        for (int64_t t = 0; t < p->n_tiles; ++t) {
+            int r = p->tile_row[t], c = p->tile_col[t];
+            int nr = p->nfun[r], ncl = p->nfun[c];
+            for (int i = 0; i < nr; ++i) {
+                int64_t row = cs[r] + i;
+                const int32_t *b = col + rp[row], *e = col + rp[row + 1];
+                for (int j = 0; j < ncl; ++j) {
+                    int32_t cc = (int32_t)(cs[c] + j);
+                    const int32_t *f = std::lower_bound(b, e, cc);
+                    if (f < e && *f == cc) p->csr_pos[p->tile_off[t] + (int64_t)j * nr + i] = rp[row] + (f - col - rp[row]);
+                }
+            }
+        }
+        p->masked = p->nnz != p->n_stored;
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(SPM_ENOMEM, "host allocation");
+    }
+    if ((st = spm::upload_pattern_device(p, (hipStream_t)stream))) {
+        spm::free_pattern_device(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return SPM_OK;
+}
+
+extern "C" int spm_pattern_destroy(spm_pattern p)
+{
+    if (!p) return SPM_OK;
+    spm::free_pattern_device(p);
+    delete p;
+    return SPM_OK;
+}
+
+extern "C" int spm_pattern_info(spm_pattern p, int64_t *nnz, int64_t *n_stored, int64_t *n_tiles, double *macs)
+{
+    if (!p) return fail(SPM_EINVAL, "spm_pattern_info: null pattern");
+    if (nnz) *nnz = p->nnz;
+    if (n_stored) *n_stored = p->n_stored;
+    if (n_tiles) *n_tiles = p->n_tiles;
+    if (macs) *macs = p->macs;
+    return SPM_OK;
+}
+
+extern "C" int spm_pattern_tiles(spm_pattern p, int32_t *tr, int32_t *tc, int64_t *to)
+{
+    if (!p) return fail(SPM_EINVAL, "spm_pattern_tiles: null pattern");
+    if (tr) std::copy(p->tile_row.begin(), p->tile_row.end(), tr);
+    if (tc) std::copy(p->tile_col.begin(), p->tile_col.end(), tc);
+    if (to) std::copy(p->tile_off.begin(), p->tile_off.end() - 1, to);
+    return SPM_OK;
+}
+
+extern "C" int spm_pattern_download_csr(spm_pattern p, int64_t *rp, int32_t *col)
+{
+    if (!p || !rp || !col) return fail(SPM_EINVAL, "spm_pattern_download_csr: null pointer");
+    if (!p->csr_rp.empty()) {
+        std::copy(p->csr_rp.begin(), p->csr_rp.end(), rp);
+        std::copy(p->csr_col.begin(), p->csr_col.end(), col);
+        return SPM_OK;
+    }
+    rp[0] = 0;
+    int64_t e = 0;
+    for (int r = 0; r < p->nc; ++r)
+        for (int i = 0; i < p->nfun[r]; ++i) {
+            for (int64_t t = p->blk_rp[r]; t < p->blk_rp[r + 1]; ++t) {
+                int c = p->tile_col[t];
+                for (int j = 0; j < p->nfun[c]; ++j) col[e++] = (int32_t)(p->cstart[c] + j);
+            }
+            rp[p->cstart[r] + i + 1] = e;
+        }
+    return SPM_OK;
+}

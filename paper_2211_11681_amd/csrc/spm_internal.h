@@ -1,0 +1,90 @@
+// Internal declarations shared by the host and device translation units of libspm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spm.h"
+
+namespace spm {
+
+constexpr int kMaxFun = 32;   // largest number of basis functions per cluster the kernels take
+
+int fail(int status, const std::string &msg);   // records msg, returns status
+
+#define SPM_HIP(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::spm::fail(SPM_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device copy of a host vector (owned by the pattern / tree handle).
+template <typename T>
+struct DevBuf {
+    T *ptr = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace spm
+
+struct spm_tree_s {
+    int64_t n = 0;
+    int32_t d = 0, leaf = 0, q = 0, m = 0;
+    int32_t nc = 0, depth = 0;
+    std::vector<double> pts;          // tree order, n x d
+    std::vector<int64_t> perm;        // tree position -> original index
+    std::vector<int64_t> pstart, psize;
+    std::vector<int32_t> level, parent, son0, son1;
+    std::vector<double> lo, hi;       // nc x d
+    std::vector<int64_t> cstart;      // basis ranges, nc + 1
+    // two-scale transforms
+    std::vector<int32_t> nin, nscal;  // inputs and scaling functions handed up, per cluster
+    std::vector<int64_t> qoff;        // offset of each cluster's Q (nin x nin, column-major)
+    std::vector<double> qmat;
+    std::vector<int64_t> slotoff;     // offset of each cluster's input slot list
+    std::vector<int64_t> slots;       // input slots (tree-order point positions)
+};
+
+struct spm_pattern_s {
+    int64_t n = 0, nnz = 0, n_stored = 0, n_tiles = 0;
+    int32_t nc = 0;
+    double macs = 0.0;
+    bool masked = false;              // some tile positions are outside S
+    int32_t max_rowlen = 0;           // longest block row (tiles)
+    // host structure
+    std::vector<int64_t> cstart;      // nc + 1
+    std::vector<int32_t> nfun;        // nc
+    std::vector<int64_t> blk_rp;      // nc + 1
+    std::vector<int32_t> tile_row, tile_col, trans;   // n_tiles
+    std::vector<int64_t> tile_off;    // n_tiles + 1
+    std::vector<int64_t> colprefix;   // n_tiles: entries of the tile row before this tile
+    std::vector<int64_t> rowbase, rowlen;  // nc: CSR position of the block row's first entry, entries per row
+    std::vector<int32_t> diag_tile;   // nc
+    std::vector<int32_t> order;       // tile processing order (schedule)
+    // masked patterns only (entry-level upload)
+    std::vector<int64_t> csr_rp;      // n + 1
+    std::vector<int32_t> csr_col;
+    std::vector<int64_t> csr_pos;     // n_stored: CSR position or -1
+    // device copies
+    spm::DevBuf<int64_t> d_cstart, d_blk_rp, d_tile_off, d_colprefix, d_rowbase, d_rowlen, d_csr_pos;
+    spm::DevBuf<int32_t> d_nfun, d_tile_row, d_tile_col, d_trans, d_diag_tile, d_order;
+    spm::DevBuf<uint8_t> d_keep;      // n_stored, masked patterns only
+    spm::DevBuf<double> d_partial;    // reduction partials
+};
+
+namespace spm {
+int upload_pattern_device(spm_pattern_s *p, hipStream_t s);
+void free_pattern_device(spm_pattern_s *p);
+}  // namespace spm
+
+namespace spm {
+int launch_gemm(spm_pattern_s *p, int prec, const void *A, int ta, const void *B, int tb, void *C, hipStream_t s);
+int launch_reduce(spm_pattern_s *p, int op, int prec, const void *x, const void *y, const double *vec, double alpha,
+                  int post, double scale, double *out, hipStream_t s);
+int launch_axpy(spm_pattern_s *p, int prec, double alpha, const void *X, double beta, void *Y, hipStream_t s);
+int launch_convert(spm_pattern_s *p, int pf, const void *X, int pt, void *Y, hipStream_t s);
+}  // namespace spm

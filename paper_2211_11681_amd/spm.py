@@ -1,0 +1,236 @@
+"""Python binding of libspm: the same operations as include/spm.h, on torch tensors.
+
+Argument marshalling only: every step runs in libspm (host C++ or HIP kernels);
+torch provides device memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import call
+
+F64, F32SPLIT, F32ACC = 0, 1, 2
+_PREC = {"f64": F64, "f32split": F32SPLIT, "f32acc": F32ACC}
+
+
+def prec_code(prec) -> int:
+    return _PREC[prec] if isinstance(prec, str) else int(prec)
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    if a is None:
+        return ctypes.c_void_p(0)
+    if isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+class Tree:
+    """Cluster tree and samplet basis of a point set (library construction)."""
+
+    def __init__(self, points: np.ndarray, leaf_size: int, q: int):
+        pts = _host(points, np.float64)
+        n, d = pts.shape
+        h = ctypes.c_void_p()
+        call("spm_tree_build", _ptr(pts), n, d, leaf_size, q, ctypes.byref(h))
+        self._h = h
+        self.n, self.d = n, d
+        nc, depth, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        call("spm_tree_info", h, ctypes.byref(nc), ctypes.byref(depth), ctypes.byref(m))
+        self.n_clusters, self.depth, self.m = nc.value, depth.value, m.value
+
+    def arrays(self):
+        nc = self.n_clusters
+        perm = np.empty(self.n, np.int64)
+        cs = np.empty(nc + 1, np.int64)
+        lev = np.empty(nc, np.int32)
+        ps = np.empty(nc, np.int64)
+        pz = np.empty(nc, np.int64)
+        call("spm_tree_arrays", self._h, _ptr(perm), _ptr(cs), _ptr(lev), _ptr(ps), _ptr(pz))
+        return dict(perm=perm, cluster_start=cs, level=lev, pt_start=ps, pt_size=pz)
+
+    def block_pattern(self, eta: float):
+        rp = np.empty(self.n_clusters + 1, np.int64)
+        nb = ctypes.c_int64()
+        call("spm_tree_block_pattern", self._h, eta, _ptr(rp), None, ctypes.byref(nb))
+        col = np.empty(nb.value, np.int32)
+        call("spm_tree_block_pattern", self._h, eta, _ptr(rp), _ptr(col), ctypes.byref(nb))
+        return rp, col
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib._lib is not None:
+                _lib._lib.spm_tree_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Pattern:
+    """Device-resident tiled compression pattern."""
+
+    def __init__(self, handle, n: int, n_clusters: int):
+        self._h = handle
+        self.n, self.n_clusters = n, n_clusters
+        nnz, ns, nt, macs = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        call("spm_pattern_info", handle, ctypes.byref(nnz), ctypes.byref(ns), ctypes.byref(nt), ctypes.byref(macs))
+        self.nnz, self.n_stored, self.n_tiles, self.macs = nnz.value, ns.value, nt.value, macs.value
+
+    @classmethod
+    def from_blocks(cls, n, cluster_start, blk_row_ptr, blk_col):
+        cs = _host(cluster_start, np.int64)
+        rp = _host(blk_row_ptr, np.int64)
+        col = _host(blk_col, np.int32)
+        h = ctypes.c_void_p()
+        call("spm_block_pattern_upload", n, len(cs) - 1, _ptr(cs), _ptr(rp), _ptr(col), _stream(), ctypes.byref(h))
+        return cls(h, n, len(cs) - 1)
+
+    @classmethod
+    def from_csr(cls, n, row_ptr, col_idx, cluster_start):
+        rp = _host(row_ptr, np.int64)
+        col = _host(col_idx, np.int32)
+        cs = _host(cluster_start, np.int64)
+        h = ctypes.c_void_p()
+        call("spm_compress_pattern_upload", n, _ptr(rp), _ptr(col), len(cs) - 1, _ptr(cs), _stream(), ctypes.byref(h))
+        return cls(h, n, len(cs) - 1)
+
+    @classmethod
+    def from_tree(cls, tree: Tree, eta: float):
+        rp, col = tree.block_pattern(eta)
+        return cls.from_blocks(tree.n, tree.arrays()["cluster_start"], rp, col)
+
+    def tiles(self):
+        tr = np.empty(self.n_tiles, np.int32)
+        tc = np.empty(self.n_tiles, np.int32)
+        to = np.empty(self.n_tiles, np.int64)
+        call("spm_pattern_tiles", self._h, _ptr(tr), _ptr(tc), _ptr(to))
+        return tr, tc, to
+
+    def download_csr(self):
+        rp = np.empty(self.n + 1, np.int64)
+        col = np.empty(self.nnz, np.int32)
+        call("spm_pattern_download_csr", self._h, _ptr(rp), _ptr(col))
+        return rp, col
+
+    def empty(self, prec="f64", device="cuda") -> torch.Tensor:
+        p = prec_code(prec)
+        if p == F64:
+            return torch.empty(self.n_stored, dtype=torch.float64, device=device)
+        return torch.empty(self.n_stored * (2 if p == F32SPLIT else 1), dtype=torch.float32, device=device)
+
+    def values_from_csr(self, csr_vals: torch.Tensor) -> torch.Tensor:
+        out = self.empty("f64")
+        call("spm_values_from_csr", self._h, _ptr(csr_vals), _ptr(out), _stream())
+        return out
+
+    def values_to_csr(self, vals: torch.Tensor) -> torch.Tensor:
+        out = torch.zeros(self.nnz, dtype=torch.float64, device=vals.device)
+        call("spm_values_to_csr", self._h, _ptr(vals), _ptr(out), _stream())
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib._lib is not None:
+                _lib._lib.spm_pattern_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def kernel_compress(pat: Pattern, tree: Tree, matern_p: int, ell: float, scale: float, deriv: bool = False,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    out = pat.empty("f64") if out is None else out
+    call("spm_kernel_compress", pat._h, tree._h, matern_p, ell, scale, int(deriv), _ptr(out), _stream())
+    return out
+
+
+def masked_gemm(pat: Pattern, A, B, transA=False, transB=False, prec="f64", out=None) -> torch.Tensor:
+    p = prec_code(prec)
+    out = pat.empty(p) if out is None else out
+    call("spm_masked_gemm", pat._h, p, _ptr(A), int(transA), _ptr(B), int(transB), _ptr(out), _stream())
+    return out
+
+
+def masked_gemm_backward(pat: Pattern, dC, A, B, need_a=True, need_b=True, prec="f64"):
+    p = prec_code(prec)
+    dA = pat.empty(p) if need_a else None
+    dB = pat.empty(p) if need_b else None
+    call("spm_masked_gemm_backward", pat._h, p, _ptr(dC), _ptr(A), _ptr(B), _ptr(dA), _ptr(dB), _stream())
+    return dA, dB
+
+
+def axpy(pat: Pattern, alpha: float, X, beta: float, Y: torch.Tensor, prec="f64") -> torch.Tensor:
+    """Y <- alpha X + beta Y in place (X = None: the identity)."""
+    call("spm_axpy", pat._h, prec_code(prec), alpha, _ptr(X), beta, _ptr(Y), _stream())
+    return Y
+
+
+def convert(pat: Pattern, X, prec_from, prec_to) -> torch.Tensor:
+    out = pat.empty(prec_to)
+    call("spm_convert", pat._h, prec_code(prec_from), _ptr(X), prec_code(prec_to), _ptr(out), _stream())
+    return out
+
+
+def _scalar(dev) -> torch.Tensor:
+    return torch.empty(1, dtype=torch.float64, device=dev)
+
+
+def sqdist(pat: Pattern, X, Y=None, prec="f64") -> torch.Tensor:
+    out = _scalar(X.device)
+    call("spm_sqdist", pat._h, prec_code(prec), _ptr(X), _ptr(Y), _ptr(out), _stream())
+    return out
+
+
+def sqdist_eye(pat: Pattern, X, alpha=1.0, prec="f64") -> torch.Tensor:
+    out = _scalar(X.device)
+    call("spm_sqdist_eye", pat._h, prec_code(prec), alpha, _ptr(X), _ptr(out), _stream())
+    return out
+
+
+def dot(pat: Pattern, X, Y) -> torch.Tensor:
+    out = _scalar(X.device)
+    call("spm_dot", pat._h, _ptr(X), _ptr(Y), _ptr(out), _stream())
+    return out
+
+
+def quadform(pat: Pattern, X, y) -> torch.Tensor:
+    out = _scalar(X.device)
+    call("spm_quadform", pat._h, _ptr(X), _ptr(y), _ptr(out), _stream())
+    return out
+
+
+def fill_outer(pat: Pattern, y, alpha=1.0, out=None) -> torch.Tensor:
+    out = pat.empty("f64") if out is None else out
+    call("spm_fill_outer", pat._h, alpha, _ptr(y), _ptr(out), _stream())
+    return out
+
+
+def newton_schulz(pat: Pattern, A: torch.Tensor, iters: int, n_final_f64: int = 3, bulk="f64",
+                  alpha0: float = 1.0, checkpoints: bool = False):
+    """Masked Newton-Schulz; returns (X, residuals[iters+1], list of X_0..X_iters or None)."""
+    b = prec_code(bulk)
+    need = ctypes.c_size_t()
+    call("spm_newton_schulz_scratch", pat._h, b, ctypes.byref(need))
+    scratch = torch.empty((need.value + 7) // 8, dtype=torch.float64, device=A.device)
+    X = pat.empty("f64")
+    res = torch.empty(iters + 1, dtype=torch.float64, device=A.device)
+    ck = None
+    ck_arr = None
+    if checkpoints:
+        ck = [pat.empty("f64") for _ in range(iters + 1)]
+        ck_arr = (ctypes.c_void_p * (iters + 1))(*[c.data_ptr() for c in ck])
+    call("spm_newton_schulz", pat._h, _ptr(A), _ptr(X), iters, n_final_f64, b, alpha0, _ptr(res),
+         ck_arr if ck_arr is not None else None, _ptr(scratch), scratch.numel() * 8, _stream())
+    return X, res, ck
