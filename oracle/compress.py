@@ -43,12 +43,13 @@ def compress_dense(basis: SampletBasis, p: int, ell: float, scale: float, deriv:
 
 
 def compress_rows(basis: SampletBasis, rows: np.ndarray, p: int, ell: float, scale: float,
-                  deriv: bool = False, T=None, chunk: int = 1 << 24) -> np.ndarray:
+                  deriv: bool = False, T=None, chunk: int = 1 << 24, use_c: bool = False) -> np.ndarray:
     """Rows ``rows`` of K^Sigma (dense, len(rows) x N) without forming K.
 
     Row b of K^Sigma is T (K omega_b): first the kernel is applied to the
     coefficient vector omega_b (only the points of b's cluster contribute),
     then the samplet transform T maps the result to samplet coordinates.
+    ``use_c`` evaluates the kernel sums with the oracle's plain C helper.
     """
     t = basis.tree
     n = int(t.size[0])
@@ -62,11 +63,15 @@ def compress_rows(basis: SampletBasis, rows: np.ndarray, p: int, ell: float, sca
         c = owner[b]
         s, sz = int(t.start[c]), int(t.size[c])
         w = np.asarray(basis.coef[c])[b - basis.cluster_start[c]]
-        acc = np.zeros(n)
-        step = max(1, chunk // max(sz, 1))
-        for j0 in range(0, n, step):
-            j1 = min(n, j0 + step)
-            kk = f(pairwise_dist(x[j0:j1], x[s:s + sz])) * scale   # (j1-j0, sz)
-            acc[j0:j1] = kk @ w
+        if use_c:
+            from . import native
+            acc = native.kernel_apply(x, x[s:s + sz], w, p, ell, scale, deriv)
+        else:
+            acc = np.zeros(n)
+            step = max(1, chunk // max(sz, 1))
+            for j0 in range(0, n, step):
+                j1 = min(n, j0 + step)
+                kk = f(pairwise_dist(x[j0:j1], x[s:s + sz])) * scale   # (j1-j0, sz)
+                acc[j0:j1] = kk @ w
         out[k] = T @ acc
     return out
