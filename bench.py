@@ -1,0 +1,208 @@
+"""Benchmark of the S-format masked product on one MI355X.
+
+Workload (the product benchmark of the paper's numerical results, Section 5.1,
+at the sizes of this build's headline configuration): N = 131072 points i.i.d.
+uniform in the unit cube [0,1]^3 (seed 2), exponential kernel (Matern nu = 1/2)
+with lengthscale 0.3 scaled by 1/N, samplets with vanishing moments up to
+degree 1 (m = 4), leaf size 32, eta = 1.0.  K = P_S(T K T^T) is built on the
+device before timing.
+
+One step = the whole hot path on one batch of input:
+    C = P_S(K K)            (spm_masked_gemm, FP64)
+    Y = K + 0.1 I           (spm_axpy: copy of K, then the identity on the diagonal)
+
+Output: one JSON line.  value = pattern entries of C per second (whole job,
+inputs resident in HBM).  roofline: the product kernel's algorithmic FP64 flops
+(2 x the exact multiply-adds over the tile structure) per launch divided by its
+average duration from HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(workload="samplet_masked_product_cube3", n=131072, dim=3, kernel="matern_nu0.5", lengthscale=0.3,
+                vanishing_moments_degree=1, leaf=32, eta=1.0, seed=2)
+
+PEAK_FP64 = 78.6      # TFLOP/s, MI355X FP64 vector and matrix
+PEAK_HBM = 8000.0     # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="override N (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(points, leaf, q, eta, threads):
+    """Oracle's sorted-merge product timed on the host over a bounded row sample.
+
+    Sample: all basis rows of six clusters (three leaves at a quarter, half and
+    three quarters of the leaf order, and the middle clusters of the levels two,
+    four and six above the leaves); their output entries
+    c_ij = sum_{k in S_i cap S_j} a_ik b_kj are computed by the oracle's plain C
+    merge with synthetic operand values (the pattern, not the values, sets the
+    work)."""
+    import numpy as np
+
+    import synth
+    from oracle import native, pattern, samplets, tree
+
+    ot = tree.build_tree(points, leaf)
+    ob = samplets.build_samplets(ot, q)
+    blocks = pattern.block_pattern(ot, eta)
+    cs = ob.cluster_start
+    n = int(cs[-1])
+    nf = np.diff(cs)
+    leaves = np.nonzero(ot.sons[:, 0] < 0)[0]
+    lv = ot.level
+    sample = [int(leaves[len(leaves) * k // 4]) for k in (1, 2, 3)]
+    for up in (2, 4, 6):
+        inner = np.nonzero(lv == max(0, ot.depth - up))[0]
+        sample.append(int(inner[len(inner) // 2]))
+    need = sorted(set(np.concatenate([blocks[c] for c in sample]).tolist()) | set(sample))
+    rowlen = np.zeros(n, np.int64)
+    cols_of = {}
+    for c in need:
+        cc = np.concatenate([np.arange(cs[b], cs[b + 1]) for b in blocks[c]]).astype(np.int32)
+        cols_of[c] = cc
+        rowlen[cs[c]:cs[c + 1]] = len(cc)
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(rowlen)
+    col = np.empty(rp[-1], np.int32)
+    rows_i = np.repeat(np.arange(n), rowlen)
+    for c in need:
+        for i in range(cs[c], cs[c + 1]):
+            col[rp[i]:rp[i + 1]] = cols_of[c]
+    a = 2.0 * synth.pair_uniform(11, rows_i, col, n) - 1.0
+    bt = 2.0 * synth.pair_uniform(12, col, rows_i, n) - 1.0      # bt[pos(j,k)] = b_kj
+    rows = np.concatenate([np.arange(cs[c], cs[c + 1]) for c in sample])
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    t0 = time.perf_counter()
+    _, cnt = native.masked_product_rows_bt(rows, rp, col, a, bt)
+    dt = time.perf_counter() - t0
+    return {"value": cnt / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {len(rows)} basis rows of clusters {sample} (three leaves, three internal clusters at "
+                      f"levels {[int(lv[c]) for c in sample[3:]]}): {cnt} output entries of P_S(A B) by the oracle's "
+                      f"C sorted-merge product, synthetic operand values, {dt:.2f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the product is not sharded "
+              f"across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    S._lib.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    n = args.n
+    w = WORKLOAD
+    print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
+    pts = synth.points_cube(n, w["dim"], w["seed"])
+    t0 = time.perf_counter()
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    K = S.kernel_compress(pat, tree, 0, w["lengthscale"], 1.0 / n)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] setup {t_setup:.1f} s: tiles {pat.n_tiles} nnz {pat.nnz} macs {pat.macs:.3e}",
+          file=sys.stderr, flush=True)
+    C = pat.empty("f64")
+    Y = pat.empty("f64")
+
+    def step():
+        S.masked_gemm(pat, K, K, out=C)
+        S.axpy(pat, 1.0, K, 0.0, Y)
+        S.axpy(pat, 0.1, None, 1.0, Y)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(args.steps):
+        ev[k][0].record()
+        S.masked_gemm(pat, K, K, out=C)
+        ev[k][1].record()
+        S.axpy(pat, 1.0, K, 0.0, Y)
+        S.axpy(pat, 0.1, None, 1.0, Y)
+    end.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    ms_step = ms_total / args.steps
+    ms_gemm = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, product {ms_gemm:.3f} ms", file=sys.stderr, flush=True)
+
+    flops = 2.0 * pat.macs
+    tflops = flops / (ms_gemm * 1e-3) / 1e12
+    compulsory = 3 * pat.n_stored * 8          # A, B (here the same array, counted twice as operands) and C
+    out = {
+        "metric": "pattern entries/s of P_S(A*B) (FP64), with HBM GB/s and FP32-split at stated relative error",
+        "value": pat.nnz / (ms_step * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": dict(w, n=n, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": tflops / PEAK_FP64, "traffic": None},
+        "product_ms": ms_gemm,
+        "product_compulsory_GBps": compulsory / (ms_gemm * 1e-3) / 1e9,
+        "setup_s": t_setup,
+    }
+    if not args.no_split:
+        ref_norm = S.sqdist(pat, C).item() ** 0.5
+        for prec in ("f32split", "f32acc"):
+            Ks = S.convert(pat, K, "f64", prec)
+            Cs = S.masked_gemm(pat, Ks, Ks, prec=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(1, args.steps // 2)
+            e0.record()
+            for _ in range(reps):
+                S.masked_gemm(pat, Ks, Ks, prec=prec, out=Cs)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            C64 = S.convert(pat, Cs, prec, "f64")
+            err = S.sqdist(pat, C64, C).item() ** 0.5 / ref_norm
+            out[prec] = {"product_ms": ms, "entries_per_s": pat.nnz / (ms * 1e-3), "speedup_vs_f64": ms_gemm / ms,
+                         "rel_frobenius_err_vs_f64": err}
+            del Ks, Cs, C64
+            print(f"[bench] {prec}: {ms:.3f} ms, rel err {err:.3e}", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("SPM_CPU_THREADS", min(16, os.cpu_count() or 1)))
+        out["cpu_baseline"] = cpu_baseline(pts, w["leaf"], w["vanishing_moments_degree"], w["eta"], threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

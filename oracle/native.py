@@ -84,6 +84,19 @@ def masked_product_rows(rows, rp, col, a, b, tpos=None):
     return c, int(cnt)
 
 
+def masked_product_rows_bt(rows, rp, col, a, bt):
+    """Entries of P_S(A B) on the given rows with B^T given directly on the pattern
+    (bt[pos(j, k)] = b_kj); rows not needed may be empty in rp.  Returns (c, count)."""
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    bt = np.ascontiguousarray(bt, dtype=np.float64)
+    c = np.zeros_like(a)
+    cnt = lib().oracle_masked_product_rows(rows.shape[0], _p(rows), _p(rp), _p(col), _p(a), _p(bt), _p(c))
+    return c, int(cnt)
+
+
 def kernel_apply(x: np.ndarray, y: np.ndarray, w: np.ndarray, p: int, ell: float, scale: float,
                  deriv: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
