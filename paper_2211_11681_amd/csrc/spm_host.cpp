@@ -403,6 +403,248 @@ int check_symmetric_diag(int64_t nrows, const int64_t *rp, const int32_t *col, c
     return SPM_OK;
 }
 
+inline int ceil4(int x) { return (x + 3) & ~3; }
+
+// Grouped schedule of the FP64 product.  Consecutive clusters of equal size form
+// groups of up to 4 (at most 128 rows); with clusters numbered level by level these
+// are neighbours in the tree.  A unit is a pair of groups (G_r, G_c) holding at
+// least one output tile; it sums over the clusters mu in U(G_r) cap U(G_c), where
+// U(G) is the union of the members' block rows.
+void build_groups(spm_pattern_s *p)
+{
+    const int nc = p->nc;
+    std::vector<int32_t> gid(nc, -1);
+    p->grp_mem.clear(); p->grp_s.clear(); p->grp_g.clear(); p->grp_R.clear();
+    p->kmax = 4;
+    for (int c = 0; c < nc; ++c) p->kmax = std::max(p->kmax, ceil4(p->nfun[c]));
+    int c = 0;
+    while (c < nc) {
+        if (p->nfun[c] == 0) { ++c; continue; }
+        const int s = ceil4(p->nfun[c]);
+        const int gmax = std::max(1, std::min(4, 128 / s));
+        int k = 0;
+        const int g = (int)p->grp_s.size();
+        while (c < nc && k < gmax && ceil4(p->nfun[c]) == s && p->nfun[c] > 0) {
+            p->grp_mem.push_back(c);
+            gid[c] = g;
+            ++k; ++c;
+        }
+        for (int r = k; r < 4; ++r) p->grp_mem.push_back(-1);
+        p->grp_s.push_back(s);
+        p->grp_g.push_back(k);
+        p->grp_R.push_back(((k * s) + 15) / 16 * 16);
+    }
+    const int ng = (int)p->grp_s.size();
+    p->ng = ng;
+    // union lists
+    p->gl_rp.assign(ng + 1, 0);
+    p->gl_mu.clear(); p->gl_tile.clear();
+    for (int g = 0; g < ng; ++g) {
+        std::vector<std::pair<int32_t, int32_t>> ent;    // (mu, k * 2^28 + position) sorted by mu
+        std::vector<int32_t> mus;
+        for (int k = 0; k < p->grp_g[g]; ++k) {
+            int r = p->grp_mem[g * 4 + k];
+            for (int64_t t = p->blk_rp[r]; t < p->blk_rp[r + 1]; ++t) mus.push_back(p->tile_col[t]);
+        }
+        std::sort(mus.begin(), mus.end());
+        mus.erase(std::unique(mus.begin(), mus.end()), mus.end());
+        const size_t base = p->gl_mu.size();
+        p->gl_mu.insert(p->gl_mu.end(), mus.begin(), mus.end());
+        p->gl_tile.resize((base + mus.size()) * 4, -1);
+        for (int k = 0; k < p->grp_g[g]; ++k) {
+            int r = p->grp_mem[g * 4 + k];
+            size_t e = 0;
+            for (int64_t t = p->blk_rp[r]; t < p->blk_rp[r + 1]; ++t) {
+                while (mus[e] != p->tile_col[t]) ++e;
+                p->gl_tile[(base + e) * 4 + k] = (int32_t)t;
+            }
+        }
+        p->gl_rp[g + 1] = (int64_t)p->gl_mu.size();
+    }
+    // units
+    p->unit_gr.clear(); p->unit_gc.clear(); p->unit_out.clear();
+    for (int g = 0; g < ng; ++g) {
+        std::vector<int32_t> cg;
+        for (int64_t e = p->gl_rp[g]; e < p->gl_rp[g + 1]; ++e) cg.push_back(gid[p->gl_mu[e]]);
+        cg.erase(std::unique(cg.begin(), cg.end()), cg.end());   // entries sorted by cluster -> groups ascending
+        for (int h : cg) {
+            p->unit_gr.push_back(g);
+            p->unit_gc.push_back(h);
+            int32_t out[16];
+            for (int q = 0; q < 16; ++q) out[q] = -1;
+            const int32_t *b = p->gl_mu.data() + p->gl_rp[g], *e = p->gl_mu.data() + p->gl_rp[g + 1];
+            for (int kc = 0; kc < p->grp_g[h]; ++kc) {
+                int32_t cc = p->grp_mem[h * 4 + kc];
+                const int32_t *f = std::lower_bound(b, e, cc);
+                if (f == e || *f != cc) continue;
+                int64_t ent = f - p->gl_mu.data();
+                for (int kr = 0; kr < p->grp_g[g]; ++kr) out[kr * 4 + kc] = p->gl_tile[ent * 4 + kr];
+            }
+            p->unit_out.insert(p->unit_out.end(), out, out + 16);
+        }
+    }
+    const int64_t nu = (int64_t)p->unit_gr.size();
+    // middle clusters of each unit (merge of the two union lists) and its cost:
+    // rows x cols x padded k
+    std::vector<double> cost(nu, 0.0);
+    std::vector<int64_t> cnt(nu, 0);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto merge = [&](int64_t u, int32_t *pa, int32_t *pb) {
+        int g = p->unit_gr[u], h = p->unit_gc[u];
+        const int64_t a0 = p->gl_rp[g], a1 = p->gl_rp[g + 1], b0 = p->gl_rp[h], b1 = p->gl_rp[h + 1];
+        int64_t a = a0, b = b0, k = 0, np = 0;
+        while (a < a1 && b < b1) {
+            const int32_t x = p->gl_mu[a], y = p->gl_mu[b];
+            if (x < y) ++a;
+            else if (y < x) ++b;
+            else {
+                if (pa) { pa[np] = (int32_t)a; pb[np] = (int32_t)b; }
+                ++np;
+                k += ceil4(p->nfun[x]);
+                ++a; ++b;
+            }
+        }
+        cnt[u] = np;
+        cost[u] = (double)p->grp_R[g] * p->grp_R[h] * (double)k;
+    };
+    {
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nth; ++w)
+            th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) merge(u, nullptr, nullptr); });
+        for (auto &x : th) x.join();
+    }
+    p->pair_off.assign(nu + 1, 0);
+    for (int64_t u = 0; u < nu; ++u) p->pair_off[u + 1] = p->pair_off[u] + cnt[u];
+    p->pair_a.resize(p->pair_off[nu]);
+    p->pair_b.resize(p->pair_off[nu]);
+    {
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nth; ++w)
+            th.emplace_back([&, w]() {
+                for (int64_t u = w; u < nu; u += nth) merge(u, p->pair_a.data() + p->pair_off[u], p->pair_b.data() + p->pair_off[u]);
+            });
+        for (auto &x : th) x.join();
+    }
+    p->padded_macs = 0.0;
+    for (double x : cost) p->padded_macs += x;
+    // per union entry: cluster size and the element offsets of the member tiles and their transposes
+    const int64_t ne = (int64_t)p->gl_mu.size();
+    p->gl_nm.resize(ne);
+    p->gl_offd.assign(ne * 4, -1);
+    p->gl_offt.assign(ne * 4, -1);
+    for (int64_t e = 0; e < ne; ++e) {
+        p->gl_nm[e] = p->nfun[p->gl_mu[e]];
+        for (int k = 0; k < 4; ++k) {
+            const int32_t t = p->gl_tile[e * 4 + k];
+            if (t < 0) continue;
+            p->gl_offd[e * 4 + k] = p->tile_off[t];
+            p->gl_offt[e * 4 + k] = p->tile_off[p->trans[t]];
+        }
+    }
+    // stages: consecutive middle clusters of a unit packed while their padded sizes sum to at most 32
+    std::vector<int64_t> nst(nu, 0);
+    auto pack = [&](int64_t u, int32_t *out) {
+        int64_t ns = 0;
+        int kacc = 0, np = 0;
+        const int64_t f0 = p->pair_off[u], f1 = p->pair_off[u + 1];
+        for (int64_t f = f0; f < f1; ++f) {
+            const int km = ceil4(p->gl_nm[p->pair_a[f]]);
+            if (np == 0 || kacc + km > 32 || np == 8) {
+                if (out) out[ns] = (int32_t)(f - f0);
+                ++ns;
+                kacc = 0;
+                np = 0;
+            }
+            kacc += km;
+            ++np;
+        }
+        nst[u] = ns;
+    };
+    {
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nth; ++w)
+            th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) pack(u, nullptr); });
+        for (auto &x : th) x.join();
+    }
+    p->stage_off.assign(nu + 1, 0);
+    for (int64_t u = 0; u < nu; ++u) p->stage_off[u + 1] = p->stage_off[u] + nst[u];
+    p->stage_first.resize(p->stage_off[nu]);
+    {
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nth; ++w)
+            th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) pack(u, p->stage_first.data() + p->stage_off[u]); });
+        for (auto &x : th) x.join();
+    }
+    // launch classes by (row blocks, column blocks).  Inside a class the units that share
+    // the wider operand panel (rows of G_r when R >= C, else columns of G_c) run back to
+    // back on one XCD so that the panel's tiles are re-read from that XCD's L2:
+    // workgroups go to the 8 XCDs round robin, so the launch order interleaves eight
+    // lists, list x holding the units whose wide group g has g % 8 == x, ordered by g.
+    std::vector<int64_t> idx(nu);
+    for (int64_t u = 0; u < nu; ++u) idx[u] = u;
+    auto key = [&](int64_t u) { return p->grp_R[p->unit_gr[u]] / 16 * 16 + p->grp_R[p->unit_gc[u]] / 16; };
+    auto wide = [&](int64_t u) {
+        return p->grp_R[p->unit_gr[u]] >= p->grp_R[p->unit_gc[u]] ? p->unit_gr[u] : p->unit_gc[u];
+    };
+    auto narrow = [&](int64_t u) {
+        return p->grp_R[p->unit_gr[u]] >= p->grp_R[p->unit_gc[u]] ? p->unit_gc[u] : p->unit_gr[u];
+    };
+    std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+        int kx = key(x), ky = key(y);
+        if (kx != ky) return kx < ky;
+        int wx = wide(x) % 8, wy = wide(y) % 8;
+        if (wx != wy) return wx < wy;
+        if (wide(x) != wide(y)) return wide(x) < wide(y);
+        return narrow(x) < narrow(y);
+    });
+    {
+        std::vector<int64_t> out;
+        out.reserve(nu);
+        int64_t c0 = 0;
+        while (c0 < nu) {
+            int64_t c1 = c0;
+            while (c1 < nu && key(idx[c1]) == key(idx[c0])) ++c1;
+            std::vector<int64_t> lo(9, c0);      // list x = idx[lo[x] .. lo[x+1])
+            for (int64_t i = c0; i < c1; ++i) lo[wide(idx[i]) % 8 + 1] = i + 1;
+            for (int x = 1; x <= 8; ++x) lo[x] = std::max(lo[x], lo[x - 1]);
+            std::vector<int64_t> pos(lo.begin(), lo.begin() + 8);
+            for (int64_t n = c0; n < c1; ++n) {
+                int x = (int)((n - c0) % 8);
+                if (pos[x] >= lo[x + 1]) {       // list exhausted: take from the longest remaining one
+                    int best = 0;
+                    for (int y = 1; y < 8; ++y)
+                        if (lo[y + 1] - pos[y] > lo[best + 1] - pos[best]) best = y;
+                    x = best;
+                }
+                out.push_back(idx[pos[x]++]);
+            }
+            c0 = c1;
+        }
+        idx.swap(out);
+    }
+    p->unit_order.resize(nu);
+    p->launches.clear();
+    for (int64_t i = 0; i < nu; ++i) {
+        p->unit_order[i] = (int32_t)idx[i];
+        int k = key(idx[i]);
+        if (p->launches.empty() || key(p->unit_order[p->launches.back().first]) != k) {
+            spm_pattern_s::Launch L;
+            L.rb = k / 16;
+            L.cb = k % 16;
+            L.waves = L.rb * L.cb == 1 ? 1 : 4;
+            L.first = i;
+            L.count = 0;
+            L.smax_r = 0;
+            L.smax_c = 0;
+            p->launches.push_back(L);
+        }
+        auto &B = p->launches.back();
+        B.count++;
+        B.smax_r = std::max(B.smax_r, p->grp_s[p->unit_gr[idx[i]]]);
+        B.smax_c = std::max(B.smax_c, p->grp_s[p->unit_gc[idx[i]]]);
+    }
+}
+
 // Fill the layout of p from its block CSR (p->blk_rp, p->tile_col, p->nfun set).
 void build_layout(spm_pattern_s *p)
 {
@@ -465,6 +707,7 @@ void build_layout(spm_pattern_s *p)
     // schedule: tiles in storage order (one workgroup per output tile)
     p->order.resize(nt);
     for (int64_t t = 0; t < nt; ++t) p->order[t] = (int32_t)t;
+    build_groups(p);
 }
 
 }  // namespace

@@ -65,6 +65,29 @@ struct spm_pattern_s {
     std::vector<int64_t> rowbase, rowlen;  // nc: CSR position of the block row's first entry, entries per row
     std::vector<int32_t> diag_tile;   // nc
     std::vector<int32_t> order;       // tile processing order (schedule)
+    // grouped schedule of the FP64 product: groups of up to 4 consecutive clusters of
+    // one size, and units = pairs of groups holding at least one output tile
+    int32_t ng = 0, kmax = 4;         // groups, largest padded cluster size
+    std::vector<int32_t> grp_mem;     // ng x 4 member clusters (-1 pads)
+    std::vector<int32_t> grp_s, grp_g, grp_R;   // slot size, member count, rows (multiple of 16)
+    std::vector<int64_t> gl_rp;       // ng + 1: union lists U(G) = union of the members' block rows
+    std::vector<int32_t> gl_mu;       // cluster of each union entry
+    std::vector<int32_t> gl_tile;     // entries x 4: tile (member k, mu) or -1
+    std::vector<int32_t> unit_gr, unit_gc, unit_out;   // units; unit_out: units x 16 output tiles or -1
+    std::vector<int32_t> unit_order;  // unit ids grouped by launch class, costly first
+    std::vector<int64_t> pair_off;    // units + 1: offsets of each unit's middle-cluster list
+    std::vector<int32_t> pair_a, pair_b;   // union-list entries of mu in U(G_r) and U(G_c)
+    std::vector<int32_t> gl_nm;       // functions of the cluster of each union entry
+    std::vector<int64_t> gl_offd, gl_offt;   // entries x 4: element offset of tile (member, mu) and of its transpose, -1 absent
+    std::vector<int64_t> stage_off;   // units + 1: stages of each unit
+    std::vector<int32_t> stage_first; // first pair of each stage, relative to the unit's pair_off
+    struct Launch {
+        int32_t rb, cb, waves;
+        int32_t smax_r, smax_c;   // largest slot of the row / column groups of the class
+        int64_t first, count;
+    };
+    std::vector<Launch> launches;
+    double padded_macs = 0.0;         // multiply-adds the grouped kernel issues (incl. padding)
     // masked patterns only (entry-level upload)
     std::vector<int64_t> csr_rp;      // n + 1
     std::vector<int32_t> csr_col;
@@ -72,6 +95,10 @@ struct spm_pattern_s {
     // device copies
     spm::DevBuf<int64_t> d_cstart, d_blk_rp, d_tile_off, d_colprefix, d_rowbase, d_rowlen, d_csr_pos;
     spm::DevBuf<int32_t> d_nfun, d_tile_row, d_tile_col, d_trans, d_diag_tile, d_order;
+    spm::DevBuf<int32_t> d_grp_mem, d_grp_s, d_grp_g, d_grp_R, d_gl_mu, d_gl_tile, d_unit_gr, d_unit_gc, d_unit_out,
+        d_unit_order;
+    spm::DevBuf<int64_t> d_gl_rp, d_pair_off, d_gl_offd, d_gl_offt, d_stage_off;
+    spm::DevBuf<int32_t> d_pair_a, d_pair_b, d_gl_nm, d_stage_first;
     spm::DevBuf<uint8_t> d_keep;      // n_stored, masked patterns only
     spm::DevBuf<double> d_partial;    // reduction partials
 };

@@ -104,6 +104,31 @@ def test_product_cfg1_vs_oracle(S, cfg1, ta, tb):
     assert np.array_equal(_dense_from_tiles(pat, C, n, cfg1["basis"].cluster_start)[~mask], np.zeros((~mask).sum()))
 
 
+PRODUCT_CASES = [("cube3", 4096, 32, 1, 1.0, 2), ("cube2", 4096, 32, 2, 1.6, 3), ("sphere", 4096, 32, 1, 1.0, 5),
+                 ("cube3", 3000, 32, 1, 1.0, 4), ("cube2", 2048, 16, 1, 0.5, 7)]
+
+
+@pytest.mark.parametrize("kind,n,leaf,q,eta,seed", PRODUCT_CASES)
+def test_product_patterns_vs_oracle(S, kind, n, leaf, q, eta, seed):
+    # block patterns of several shapes (tile sizes 4..28, root of 2m, unbalanced trees)
+    # with non-symmetric random operands, all four transpose variants
+    print(f"case: product {kind} n={n} leaf={leaf} q={q} eta={eta}", flush=True)
+    pts = synth.workload_points(kind, n, seed)
+    t = S.Tree(pts, leaf, q)
+    pat = S.Pattern.from_tree(t, eta)
+    rp, col = pat.download_csr()
+    mask = pattern.dense_mask(rp, col, n)
+    i, j = np.nonzero(mask)
+    a = np.zeros((n, n)); b = np.zeros((n, n))
+    a[i, j] = 2 * synth.pair_uniform(31, i, j, n) - 1
+    b[i, j] = 2 * synth.pair_uniform(32, i, j, n) - 1
+    A, B = pat.values_from_csr(to_dev(a[mask])), pat.values_from_csr(to_dev(b[mask]))
+    for ta, tb in [(0, 0), (0, 1), (1, 0), (1, 1)]:
+        C = S.masked_gemm(pat, A, B, transA=bool(ta), transB=bool(tb))
+        ref = ops.masked_product(a.T if ta else a, b.T if tb else b, mask)[mask]
+        assert relerr(pat.values_to_csr(C).cpu().numpy(), ref) < TOL64, (ta, tb)
+
+
 def test_product_identity_exact(S, cfg1):
     pat, mask = cfg1["pat"], cfg1["mask"]
     a = np.where(mask, cfg1["ks"], 0.0)
