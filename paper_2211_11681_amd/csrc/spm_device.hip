@@ -69,7 +69,6 @@ int upload_pattern_device(spm_pattern_s *p, hipStream_t s)
     if ((st = to_device(p->d_pair_b, p->pair_b, s))) return st;
     if ((st = to_device(p->d_gl_nm, p->gl_nm, s))) return st;
     if ((st = to_device(p->d_gl_offd, p->gl_offd, s))) return st;
-    if ((st = to_device(p->d_gl_offt, p->gl_offt, s))) return st;
     if ((st = to_device(p->d_stage_off, p->stage_off, s))) return st;
     if ((st = to_device(p->d_stage_first, p->stage_first, s))) return st;
     if (!p->csr_pos.empty()) {
@@ -94,7 +93,7 @@ void free_pattern_device(spm_pattern_s *p)
     release(p->d_grp_mem); release(p->d_grp_s); release(p->d_grp_g); release(p->d_grp_R); release(p->d_gl_rp);
     release(p->d_gl_mu); release(p->d_gl_tile); release(p->d_unit_gr); release(p->d_unit_gc); release(p->d_unit_out);
     release(p->d_unit_order); release(p->d_pair_off); release(p->d_pair_a); release(p->d_pair_b);
-    release(p->d_gl_nm); release(p->d_gl_offd); release(p->d_gl_offt); release(p->d_stage_off); release(p->d_stage_first);
+    release(p->d_gl_nm); release(p->d_gl_offd); release(p->d_stage_off); release(p->d_stage_first);
 }
 
 }  // namespace spm
@@ -422,28 +421,27 @@ __global__ void k_apply_keep(int64_t ns, int prec, const uint8_t *__restrict__ k
 
 
 // ------------------------------------------------------------------ grouped MFMA product (FP64)
+// Computes C = P_S(A B^T) for A and B in the tile layout (the callers transpose
+// operands beforehand so that every product has this form).
+//
 // One unit (G_r, G_c) = the output tiles between the (up to 4) row clusters of G_r
 // and the column clusters of G_c, held as 16x16 blocks of MFMA accumulators.  The
 // unit's middle clusters mu (U(G_r) cap U(G_c), listed by the schedule builder) come
 // in stages of consecutive clusters with at most 32 padded k rows.  Per stage the
-// panels op(A)_{G_r,mu} (R x k) and op(B)_{mu,G_c} (k x C) of all its clusters are
-// gathered into LDS by direct global-to-LDS loads (one dword per lane, 32 doubles per
-// wave instruction; absent tiles and padding read a zero word) and multiplied with
-// v_mfma_f64_16x16x4f64 (lane l: A row l%16 and k l/16, B column l%16 and k l/16;
-// accumulator register r holds row 4r + l/16, column l%16).
-// Panel layouts follow the source tiles so that the gathers read contiguous memory:
-//   row-fast  [k][x], stride Xp = x rounded up to 32: one instruction = 32 x of one k
-//             (tiles whose element order runs along x: op(A) = A, op(B) = B^T)
-//   k-fast    [x][k], stride 33: one instruction = 32 k of one x
-//             (tiles whose element order runs along k: op(A) = A^T, op(B) = B, and
-//             every panel of clusters with at most 8 functions)
-// The panels are double-buffered: the gathers of stage s+1 and the stage table of
-// stage s+2 are in flight while the MFMAs of stage s run.
-// WAVES = 8: one workgroup per unit.  WAVES = 1: one wavefront per unit, four units
-// per workgroup, each with its own LDS; no workgroup barriers.
+// panels A_{G_r,mu} (R x k) and (B_{G_c,mu})^T (k x C) are gathered into LDS, k-major
+// with row stride Xa (Xb), a power of two, by direct global-to-LDS loads: every tile
+// of the layout is column-major, so consecutive panel rows of one k are consecutive
+// source elements.  WIDTH = 16: two doubles per lane, 128 per wave instruction (all
+// cluster sizes even); WIDTH = 4: one dword per lane, 32 doubles per instruction.
+// Absent tiles and padding read a zero word.  The panels feed v_mfma_f64_16x16x4f64
+// (lane l: A row l%16 and k l/16, B column l%16 and k l/16; accumulator register r
+// holds row 4r + l/16, column l%16).  Panels are double-buffered: the gathers of
+// stage s+1 and the stage records of stage s+2 are in flight while the MFMAs of
+// stage s run; the records are fetched in three dependent steps spread over three
+// stages.  WAVES = 8: big units; WAVES = 1: 16 x 16 units.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__device__ double g_zero_word[2];   // zero-initialised source of padding
+__device__ double g_zero_word[2];   // zero-initialised source of padding (16 bytes)
 
 struct GroupArgs {
     const int32_t *grp_mem, *grp_s, *grp_g;
@@ -451,43 +449,28 @@ struct GroupArgs {
     const int64_t *pair_off;
     const int32_t *pair_a, *pair_b;
     const int32_t *gl_nm;
-    const int64_t *gl_offd, *gl_offt;
+    const int64_t *gl_offd;
     const int64_t *stage_off;
     const int32_t *stage_first;
     const int64_t *tile_off;
     const int32_t *nfun;
     int64_t first, count;
     int32_t RB, CB;
-    int32_t akf, bkf;        // k-fast layout of the A / B panels for the whole launch
-    int32_t panel_doubles;   // LDS doubles of one operand buffer (A panel + B panel)
+    int32_t lxa, lxb;        // log2 of the panel row strides
 };
 
 constexpr int kKS = 32;   // k rows per stage
 constexpr int kSP = 8;    // middle clusters per stage
-constexpr int kKF = 33;   // stride of k-fast panels
 
-struct StageTab {
-    int64_t off[kSP][8];  // element offsets: slots 0..3 op(A) tiles of the row members, 4..7 op(B) tiles of the column members
-    int32_t nm[kSP];      // functions of each middle cluster
-    int32_t kb[kSP];      // first k row of each middle cluster in the stage
-    int32_t kmap[kKS];    // k row -> middle cluster of the stage, -1 past the end
-    int32_t ks;           // padded k rows of the stage
-    int32_t pad;
-};
-
-// Per k row records of a stage (row-fast gathers, 8-wave units only): offsets of the
-// row's middle cluster and the row inside it.
+// Stage records, one per k row: for each of the 8 member slots (0..3 row members, 4..7
+// column members) the element offset of column k of the member's tile, i.e. tile offset
+// plus (k row inside the middle cluster) x (member size); -1 where the tile is absent
+// or the row is padding.
 struct KTab {
-    int64_t koff[kKS][8];
-    int32_t knm[kKS];     // functions of the row's cluster (0 past the end)
-    int32_t kkm[kKS];     // k row inside the cluster
+    int64_t kofs[kKS][8];
+    int32_t ks;           // padded k rows of the stage
+    int32_t pad[3];
 };
-
-template <int WAVES>
-constexpr size_t unit_tab_bytes()
-{
-    return 2 * (sizeof(StageTab) + (WAVES == 8 ? sizeof(KTab) : 0));
-}
 
 template <int WAVES>
 __device__ inline void unit_sync()
@@ -497,47 +480,108 @@ __device__ inline void unit_sync()
     else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+template <int WIDTH>
 __device__ inline void lds_gather(const double *src, int half, double *dst)
 {
-    __builtin_amdgcn_global_load_lds((const void *)(reinterpret_cast<const uint32_t *>(src) + half),
-                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+    if constexpr (WIDTH == 16)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    else
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t *>(src) + half,
+                                         (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
 }
 
-template <int TA, int TB, int WAVES>
-__global__ __launch_bounds__(WAVES == 8 ? 512 : 256) void k_mgemm_grp(GroupArgs g, const double *__restrict__ A,
-                                                                     const double *__restrict__ B,
-                                                                     double *__restrict__ C)
+__device__ inline int sel4(int k, int a0, int a1, int a2, int a3)
 {
-    extern __shared__ double lds_all[];
-    constexpr int NT = WAVES * 64;                 // threads per unit
-    constexpr int UPW = WAVES == 8 ? 1 : 4;        // units per workgroup
+    return k == 0 ? a0 : k == 1 ? a1 : k == 2 ? a2 : a3;
+}
+
+// Lane constants of one gather variant: the panel row x this lane fills, as member slot
+// and row inside the member.
+struct GatherLane {
+    int slot, i;
+    bool ok;
+};
+
+__device__ inline GatherLane gather_lane(int x, int s, int ng, int n0, int n1, int n2, int n3)
+{
+    GatherLane r;
+    r.slot = x / s;
+    r.i = x - r.slot * s;
+    r.ok = r.slot < ng && r.i < sel4(r.slot & 3, n0, n1, n2, n3);
+    r.slot &= 3;
+    return r;
+}
+
+// Gathers one operand panel of a stage: instruction `ins` covers the doubles
+// [D*ins, D*ins + D) of the k-major panel with row stride 2^lx; nv = max(1, 2^lx / D)
+// lane variants.  Every load of the stage goes to LDS directly; nothing waits here.
+template <int WAVES, int WIDTH>
+__device__ inline void gather_panel(const KTab *T, int slot_base, const double *__restrict__ M,
+                                    double *panel, int ks, int lx, int wave, int dl, int half,
+                                    const GatherLane (&gl)[4], const double *zero)
+{
+    constexpr int D = WIDTH * 8;
+    constexpr int LD = WIDTH == 16 ? 7 : 5;   // log2 D
+    const int X = 1 << lx;
+    const int nins = (ks * X + D - 1) >> LD;
+    if (lx <= LD) {
+        // D >= X: lane row x is fixed, k = ins * (D / X) + (dl >> lx)
+        const GatherLane g = gl[0];
+        const int kstep = 1 << (LD - lx);
+        const char *trow = reinterpret_cast<const char *>(&T->kofs[dl >> lx][slot_base + g.slot]);
+        for (int ins = wave; ins < nins; ins += WAVES) {
+            const int64_t o = *reinterpret_cast<const int64_t *>(trow + (size_t)ins * kstep * 64);
+            const double *src = (g.ok && o >= 0) ? M + o + g.i : zero;
+            lds_gather<WIDTH>(src, half, panel + ins * D);
+        }
+    } else {
+        // D < X: variant v = ins % nv covers rows [v*D, v*D + D), k = ins / nv
+        const int lnv = lx - LD, nv = 1 << lnv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (v >= nv) break;
+            if (WAVES > 1 && WAVES >= nv && v != (wave & (nv - 1))) continue;
+            const GatherLane g = gl[v];
+            const int step = WAVES > nv ? WAVES : nv;
+            const int first = WAVES >= nv ? wave : v + wave * nv;
+            const int ins_step = WAVES >= nv ? step : WAVES * nv;
+            for (int ins = first; ins < nins; ins += ins_step) {
+                const int kk = ins >> lnv;
+                const int64_t o = T->kofs[kk][slot_base + g.slot];
+                const double *src = (g.ok && o >= 0) ? M + o + g.i : zero;
+                lds_gather<WIDTH>(src, half, panel + ins * D);
+            }
+        }
+    }
+}
+
+template <int WAVES, int WIDTH>
+__global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const double *__restrict__ A,
+                                                         const double *__restrict__ B, double *__restrict__ C)
+{
+    extern __shared__ double lds[];
     constexpr int MAXB = WAVES == 8 ? 8 : 1;       // accumulator blocks per wave
-    const int tid = threadIdx.x % NT, lane = tid & 63, wave = tid >> 6;
-    const int uslot = threadIdx.x / NT;
-    const int64_t uidx = (int64_t)blockIdx.x * UPW + uslot;
-    if (uidx >= g.count) return;                    // whole unit slot idle (tail)
-    const int R = g.RB * 16, Cc = g.CB * 16;
-    const int pd = g.panel_doubles;
-    double *lds = lds_all + (size_t)uslot * (2 * pd + unit_tab_bytes<WAVES>() / sizeof(double));
-    StageTab *tab = reinterpret_cast<StageTab *>(lds + 2 * pd);
-    KTab *ktab = reinterpret_cast<KTab *>(tab + 2);     // used when WAVES == 8
+    constexpr int D = WIDTH * 8;                   // doubles per gather instruction
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = WAVES == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t uidx = blockIdx.x;
+    if (uidx >= g.count) return;
+    const int Xa = 1 << g.lxa, Xb = 1 << g.lxb;
+    const int pd = kKS * (Xa + Xb);                // doubles of one operand buffer
+    KTab *ktab = reinterpret_cast<KTab *>(lds + 2 * pd);
 
     const int u = g.unit_order[g.first + uidx];
     const int gr = g.unit_gr[u], gc = g.unit_gc[u];
     const int sr = g.grp_s[gr], sc = g.grp_s[gc];
     const int ngr = g.grp_g[gr], ngc = g.grp_g[gc];
-    int nrk[4], nck[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        nrk[k] = k < ngr ? g.nfun[g.grp_mem[gr * 4 + k]] : 0;
-        nck[k] = k < ngc ? g.nfun[g.grp_mem[gc * 4 + k]] : 0;
-    }
-    // panel layouts (fixed per launch)
-    const bool akf = g.akf != 0, bkf = g.bkf != 0;
-    const int Rp = (R + 31) & ~31, Cp = (Cc + 31) & ~31;
-    const int asz = akf ? R * kKF : kKS * Rp;       // doubles of the A panel
-    const int a_rs = akf ? kKF : 1, a_ks = akf ? 1 : Rp;   // address = row * a_rs + k * a_ks
-    const int b_cs = bkf ? kKF : 1, b_ks = bkf ? 1 : Cp;   // address = col * b_cs + k * b_ks
+    const int nr0 = g.nfun[g.grp_mem[gr * 4]];
+    const int nr1 = ngr > 1 ? g.nfun[g.grp_mem[gr * 4 + 1]] : 0;
+    const int nr2 = ngr > 2 ? g.nfun[g.grp_mem[gr * 4 + 2]] : 0;
+    const int nr3 = ngr > 3 ? g.nfun[g.grp_mem[gr * 4 + 3]] : 0;
+    const int nc0 = g.nfun[g.grp_mem[gc * 4]];
+    const int nc1 = ngc > 1 ? g.nfun[g.grp_mem[gc * 4 + 1]] : 0;
+    const int nc2 = ngc > 2 ? g.nfun[g.grp_mem[gc * 4 + 2]] : 0;
+    const int nc3 = ngc > 3 ? g.nfun[g.grp_mem[gc * 4 + 3]] : 0;
     const int nblk = g.RB * g.CB;
     const int nsplit = (WAVES == 1 || nblk >= WAVES) ? 1 : WAVES / nblk;
     const int kslice = nsplit == 1 ? 0 : wave / nblk;
@@ -546,207 +590,144 @@ __global__ __launch_bounds__(WAVES == 8 ? 512 : 256) void k_mgemm_grp(GroupArgs 
     const int bstep = (WAVES == 8 && nblk >= WAVES) ? WAVES : 1 << 20;
     const int64_t s0 = g.stage_off[u], nst = g.stage_off[u + 1] - s0;
     const int64_t p0 = g.pair_off[u], npairs = g.pair_off[u + 1] - p0;
-    const int half = lane & 1, l2 = lane >> 1;
 
-    // row-fast rows of this lane: row = 32 * blk + l2 -> (member, index), for up to 4 blocks
-    int rkr[4], ri[4], ckc[4], cj[4];
+    // per lane gather constants (variant v covers panel rows v*D .. v*D + D - 1 when D < X)
+    const int dl = WIDTH == 16 ? 2 * lane : lane >> 1;
+    const int half = lane & 1;
+    GatherLane gla[4], glb[4];
 #pragma unroll
-    for (int bl = 0; bl < 4; ++bl) {
-        const int row = 32 * bl + l2, col = 32 * bl + l2;
-        rkr[bl] = row / sr; ri[bl] = row - rkr[bl] * sr;
-        ckc[bl] = col / sc; cj[bl] = col - ckc[bl] * sc;
+    for (int v = 0; v < 4; ++v) {
+        const int xa = D >= Xa ? (dl & (Xa - 1)) : v * D + dl;
+        const int xb = D >= Xb ? (dl & (Xb - 1)) : v * D + dl;
+        gla[v] = gather_lane(xa, sr, ngr, nr0, nr1, nr2, nr3);
+        glb[v] = gather_lane(xb, sc, ngc, nc0, nc1, nc2, nc3);
     }
+    const double *const zero = g_zero_word;
 
-    // ---- stage tables, fetched by wave 0 in three steps spread over three stages so that
-    // no load waits for another one inside a stage: bounds -> union entries -> offsets.
-    // Lane (p, slot): middle cluster p of the stage, slot 0..3 row members (op(A)),
-    // 4..7 column members (op(B)); slot 0 also carries the cluster size.
+    // ---- stage records, fetched by wave 0 in three steps (bounds -> union entries ->
+    // offsets), one step per stage; each step only consumes loads of earlier stages, so
+    // no stage waits for its own loads.  Lane (p, slot): middle cluster p of the stage,
+    // slot 0..3 row members, 4..7 column members; slot 0 also carries the cluster size.
     const int tp = lane >> 3, tslot = lane & 7, tk = tslot & 3;
-    auto bounds = [&](int64_t st, int64_t &fb, int &np) {
-        fb = 0;
-        np = 0;
-        if (wave != 0 || st >= nst) return;
-        fb = g.stage_first[s0 + st];
-        const int64_t fe = st + 1 < nst ? g.stage_first[s0 + st + 1] : npairs;
-        np = (int)(fe - fb);
+    const bool tvalid = tslot < 4 ? tk < ngr : tk < ngc;
+    // bounds of a stage: lane 0 loads its first union entry, lane 1 the end (per lane, so
+    // that the value stays in a vector register and is only waited for at the next sync)
+    auto load_bounds = [&](int64_t st, int32_t &fbe) {
+        fbe = 0;
+        if (wave != 0 || st >= nst || lane > 1) return;
+        fbe = lane == 0 || st + 1 < nst ? g.stage_first[s0 + st + lane] : (int32_t)npairs;
     };
-    auto entry = [&](int64_t fb, int np) -> int {
-        if (wave != 0 || tp >= np) return -1;
-        return tslot < 4 ? g.pair_a[p0 + fb + tp] : g.pair_b[p0 + fb + tp];
+    auto load_entry = [&](int32_t fb, int np, int32_t &e) {
+        e = -1;
+        if (wave != 0 || tp >= np) return;
+        e = tslot < 4 ? g.pair_a[p0 + fb + tp] : g.pair_b[p0 + fb + tp];
     };
-    auto offsets = [&](int e, int64_t &off, int &nm) {
+    auto load_offsets = [&](int32_t e, int64_t &off, int32_t &nm) {
         off = -1;
         nm = 0;
         if (e < 0) return;
-        if (tslot < 4 ? tk < ngr : tk < ngc) {
-            const int64_t *src = tslot < 4 ? (TA == 0 ? g.gl_offd : g.gl_offt) : (TB == 0 ? g.gl_offt : g.gl_offd);
-            off = src[(int64_t)e * 4 + tk];
-        }
+        if (tvalid) off = g.gl_offd[(int64_t)e * 4 + tk];
         if (tslot == 0) nm = g.gl_nm[e];
     };
-    auto write_tab = [&](StageTab *T, KTab *KT, int64_t t_off, int t_nm, int t_np) {
+    auto write_tab = [&](KTab *T, int64_t t_off, int t_nm, int t_np) {
         if (wave != 0) return;
         int nmv[kSP], kbv[kSP];
-        int acc = 0;
+        int kacc = 0;
 #pragma unroll
         for (int q = 0; q < kSP; ++q) {
             nmv[q] = __shfl(t_nm, q * 8);
-            kbv[q] = acc;
-            acc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
+            kbv[q] = kacc;
+            kacc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
         }
-        T->off[tp][tslot] = tp < t_np ? t_off : -1;
-        if (lane < kSP) { T->nm[lane] = lane < t_np ? nmv[lane] : 0; T->kb[lane] = kbv[lane]; }
+        const int kk = lane & 31;
+        const bool rows = lane < 32;
         int m = -1;
 #pragma unroll
         for (int q = 0; q < kSP; ++q)
-            if (q < t_np && (lane & 31) >= kbv[q] && (lane & 31) < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
-        if (lane < kKS) T->kmap[lane] = m;
-        if (lane == 0) T->ks = acc;
-        if (WAVES == 8) {
-            // per k row records: lane kk (and kk + 32 for slots 4..7) gathers the offsets of its cluster
-            const int kk = lane & 31, sb = lane < 32 ? 0 : 4;
-            const int mm = m;
+            if (q < t_np && kk >= kbv[q] && kk < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
+        const int mm = m < 0 ? 0 : m;
+        int nmm = 0, kbm = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t v = __shfl(t_off, (mm < 0 ? 0 : mm) * 8 + sb + q);
-                KT->koff[kk][sb + q] = (mm >= 0) ? v : -1;
-            }
-            if (lane < 32) {
-                KT->knm[kk] = mm >= 0 ? nmv[mm < 0 ? 0 : mm] : 0;
-                KT->kkm[kk] = mm >= 0 ? kk - kbv[mm < 0 ? 0 : mm] : 0;
-            }
+        for (int q = 0; q < kSP; ++q)
+            if (q == mm) { nmm = nmv[q]; kbm = kbv[q]; }
+        const int kkm = kk - kbm;
+        const bool live = m >= 0 && kkm < nmm;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t o = __shfl(t_off, mm * 8 + (rows ? 0 : 4) + q);
+            const int n = rows ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
+            T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * n : -1;
         }
-    };
-
-    // ---- gathers of one stage into an operand buffer.  Rows (columns) outside the
-    // members' functions are not gathered: they only feed outputs that are dropped.
-    const double *const zero = g_zero_word;
-    auto gather = [&](const StageTab *T, const KTab *KT, double *buf) {
-        const int ks = T->ks;
-        double *pA = buf, *pB = buf + asz;
-        // k-fast panels: this lane's k row is l2 for every instruction
-        const int pi = l2 < ks ? T->kmap[l2] : -1;
-        const int nm_l = pi >= 0 ? T->nm[pi] : 0;
-        const int kkm_l = pi >= 0 ? l2 - T->kb[pi] : 0;
-        const bool kval = pi >= 0 && kkm_l < nm_l;
-        if (akf) {
-#pragma unroll
-            for (int kr = 0; kr < 4; ++kr) {
-                if (kr >= ngr) break;
-                const int n = nrk[kr];
-                const int64_t oo = kval ? T->off[pi][kr] : -1;
-                const bool ok = oo >= 0;
-                const double *base = A + (ok ? oo : 0);
-                double *dst = pA + kr * sr * kKF;
-                for (int i = wave; i < n; i += WAVES) {
-                    const double *src = ok ? base + (TA == 1 ? i * nm_l + kkm_l : kkm_l * n + i) : zero;
-                    lds_gather(src, half, dst + i * kKF);
-                }
-            }
-        } else if (WAVES == 8) {
-            const int nb = Rp >> 5;
-#pragma unroll
-            for (int bl = 0; bl < 4; ++bl) {
-                if (bl >= nb) break;
-                const int kr = rkr[bl], i = ri[bl];
-                const int n = kr == 0 ? nrk[0] : kr == 1 ? nrk[1] : kr == 2 ? nrk[2] : nrk[3];
-                const bool rv = kr < ngr && i < n;
-                for (int kk = wave; kk < ks; kk += WAVES) {
-                    const int nm = KT->knm[kk], kkm = KT->kkm[kk];
-                    const int64_t oo = KT->koff[kk][kr & 3];
-                    const double *src = (rv && oo >= 0 && kkm < nm) ? A + oo + kkm * n + i : zero;   // TA = 0 here
-                    lds_gather(src, half, pA + kk * Rp + bl * 32);
-                }
-            }
-        }
-        if (bkf) {
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc) {
-                if (kc >= ngc) break;
-                const int n = nck[kc];
-                const int64_t oo = kval ? T->off[pi][4 + kc] : -1;
-                const bool ok = oo >= 0;
-                const double *base = B + (ok ? oo : 0);
-                double *dst = pB + kc * sc * kKF;
-                for (int j = wave; j < n; j += WAVES) {
-                    const double *src = ok ? base + (TB == 0 ? j * nm_l + kkm_l : kkm_l * n + j) : zero;
-                    lds_gather(src, half, dst + j * kKF);
-                }
-            }
-        } else if (WAVES == 8) {
-            const int nb = Cp >> 5;
-#pragma unroll
-            for (int bl = 0; bl < 4; ++bl) {
-                if (bl >= nb) break;
-                const int kc = ckc[bl], j = cj[bl];
-                const int n = kc == 0 ? nck[0] : kc == 1 ? nck[1] : kc == 2 ? nck[2] : nck[3];
-                const bool cv = kc < ngc && j < n;
-                for (int kk = wave; kk < ks; kk += WAVES) {
-                    const int nm = KT->knm[kk], kkm = KT->kkm[kk];
-                    const int64_t oo = KT->koff[kk][4 + (kc & 3)];
-                    const double *src = (cv && oo >= 0 && kkm < nm) ? B + oo + kkm * n + j : zero;   // TB = 1 here
-                    lds_gather(src, half, pB + kk * Cp + bl * 32);
-                }
-            }
-        }
+        if (lane == 0) T->ks = kacc;
     };
 
     dbl4 acc[MAXB];
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int lr = lane & 15, lk = lane >> 4;
-    // owned output blocks of this wave and their operand offsets in the panels
-    int nown = 0, aoffs[MAXB], boffs[MAXB];
-#pragma unroll
-    for (int j = 0; j < MAXB; ++j) {
-        const int b = b0 + j * bstep;
-        const int rb = b / g.CB, cb = b - rb * g.CB;
-        aoffs[j] = 16 * rb * a_rs;
-        boffs[j] = 16 * cb * b_cs;
-        if (b < nblk) nown = j + 1;
-    }
 
-    // prologue: tables 0 and 1 written; registers: offsets of stage 2, entries of stage 3,
-    // bounds of stage 4
-    int64_t fb;
-    int np;
-    int64_t r_off;
-    int r_nm, r_np, r_e, r_enp;
-    int64_t r_fb;
-    int r_bnp;
+    // prologue: records of stages 0 and 1 written; in registers: offsets of stage 2,
+    // entries of stage 3, bounds of stage 4 (all loads complete at the first sync)
+    int32_t fbe, e;
+    int64_t off;
+    int32_t nm;
+    auto fb_of = [&](int32_t v) { return __builtin_amdgcn_readlane(v, 0); };
+    auto np_of = [&](int32_t v) { return __builtin_amdgcn_readlane(v, 1) - __builtin_amdgcn_readlane(v, 0); };
     for (int st = 0; st < 2; ++st) {
-        bounds(st, fb, np);
-        offsets(entry(fb, np), r_off, r_nm);
-        write_tab(&tab[st], &ktab[st], r_off, r_nm, np);
+        load_bounds(st, fbe);
+        load_entry(fb_of(fbe), np_of(fbe), e);
+        load_offsets(e, off, nm);
+        write_tab(&ktab[st], off, nm, np_of(fbe));
     }
-    bounds(2, fb, np);
-    offsets(entry(fb, np), r_off, r_nm);
-    r_np = np;
-    bounds(3, fb, np);
-    r_e = entry(fb, np);
-    r_enp = np;
-    bounds(4, r_fb, r_bnp);
+    load_bounds(2, fbe);
+    int np2 = np_of(fbe);
+    load_entry(fb_of(fbe), np2, e);
+    load_offsets(e, off, nm);                      // stage 2
+    load_bounds(3, fbe);
+    int np3 = np_of(fbe);
+    load_entry(fb_of(fbe), np3, e);                // stage 3
+    load_bounds(4, fbe);                           // stage 4
     unit_sync<WAVES>();
-    if (nst > 0) gather(&tab[0], &ktab[0], lds);
+    int ks_next = ktab[0].ks;
+    if (nst > 0) {
+        gather_panel<WAVES, WIDTH>(&ktab[0], 0, A, lds, ks_next, g.lxa, wave, dl, half, gla, zero);
+        gather_panel<WAVES, WIDTH>(&ktab[0], 4, B, lds + kKS * Xa, ks_next, g.lxb, wave, dl, half, glb, zero);
+    }
+    // Iteration s: records s+2 are written into the slot of stage s (whose gathers were
+    // issued one iteration earlier), the record loads advance by one stage, the gathers
+    // of stage s+1 are issued, then the MFMAs of stage s run.  Nothing issued in an
+    // iteration is consumed before the sync that opens the next one.
     for (int64_t s = 0; s < nst; ++s) {
-        const int ks_s = tab[s & 1].ks;             // read before table s is replaced below
-        unit_sync<WAVES>();                         // gathers of stage s done; MFMAs of stage s-1 done
-        write_tab(&tab[s & 1], &ktab[s & 1], r_off, r_nm, r_np);  // table s+2 replaces table s
-        if (s + 1 < nst) gather(&tab[(s + 1) & 1], &ktab[(s + 1) & 1], lds + ((s + 1) & 1) * pd);
-        // advance the fetch pipeline: offsets of s+3, entries of s+4, bounds of s+5
-        offsets(r_e, r_off, r_nm);
-        r_np = r_enp;
-        r_e = entry(r_fb, r_bnp);
-        r_enp = r_bnp;
-        bounds(s + 5, r_fb, r_bnp);
+        unit_sync<WAVES>();                         // gathers of stage s landed; MFMAs of s-1 done
+        const int ks_s = ks_next;
+        const int np4 = np_of(fbe);
+        const int32_t fb4 = fb_of(fbe);
+        write_tab(&ktab[s & 1], off, nm, np2);      // stage s+2
+        load_offsets(e, off, nm);                   // stage s+3
+        load_entry(fb4, np4, e);                    // stage s+4
+        load_bounds(s + 5, fbe);                    // stage s+5
+        np2 = np3;
+        np3 = np4;
+        if (s + 1 < nst) {
+            const KTab *T1 = &ktab[(s + 1) & 1];
+            double *buf = lds + ((s + 1) & 1) * pd;
+            ks_next = T1->ks;
+            gather_panel<WAVES, WIDTH>(T1, 0, A, buf, ks_next, g.lxa, wave, dl, half, gla, zero);
+            gather_panel<WAVES, WIDTH>(T1, 4, B, buf + kKS * Xa, ks_next, g.lxb, wave, dl, half, glb, zero);
+        }
         if (active) {
-            const double *sA = lds + (s & 1) * pd, *sB = sA + asz;
+            const double *sA = lds + (s & 1) * pd, *sB = sA + kKS * Xa;
             for (int k0 = 4 * kslice; k0 < ks_s; k0 += 4 * nsplit) {
-                const double *pa = sA + lr * a_rs + (k0 + lk) * a_ks;
-                const double *pb = sB + lr * b_cs + (k0 + lk) * b_ks;
+                const double *pa = sA + (k0 + lk) * Xa + lr;
+                const double *pb = sB + (k0 + lk) * Xb + lr;
 #pragma unroll
-                for (int j = 0; j < MAXB; ++j)
-                    if (j < nown) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[aoffs[j]], pb[boffs[j]], acc[j], 0, 0, 0);
+                for (int j = 0; j < MAXB; ++j) {
+                    const int b = b0 + j * bstep;
+                    if (j == 0 || b < nblk) {
+                        const int rb = b / g.CB, cb = b - rb * g.CB;
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[16 * rb], pb[16 * cb], acc[j], 0, 0, 0);
+                    }
+                }
             }
         }
     }
@@ -767,22 +748,47 @@ __global__ __launch_bounds__(WAVES == 8 ? 512 : 256) void k_mgemm_grp(GroupArgs 
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
         const int b = b0 + j * bstep;
-        if (b >= nblk) continue;
+        if (j > 0 && b >= nblk) continue;
         const int rb = b / g.CB, cb = b - rb * g.CB;
         const int col = 16 * cb + lr;
         const int kc = col / sc, jj = col - kc * sc;
-        if (kc >= ngc) continue;
-        const int ncl = nck[kc];
-        if (jj >= ncl) continue;
+        if (kc >= ngc || jj >= sel4(kc & 3, nc0, nc1, nc2, nc3)) continue;
+        const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * rb + 4 * r + lk;
             const int kr = row / sr, i = row - kr * sr;
             if (kr >= ngr) continue;
+            const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
             const int t = g.unit_out[u * 16 + kr * 4 + kc];
-            const int nr = nrk[kr];
             if (t >= 0 && i < nr) C[g.tile_off[t] + (int64_t)jj * nr + i] = acc[j][r];
         }
+    }
+}
+
+// Transpose of an S-matrix: tile (c, r) of X^T is (X_{r,c})^T.  One block per tile,
+// staged through LDS so that reads and writes are both contiguous.
+__global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
+                                                   const int32_t *__restrict__ tile_row,
+                                                   const int32_t *__restrict__ tile_col,
+                                                   const int32_t *__restrict__ trans, const int32_t *__restrict__ nfun,
+                                                   const double *__restrict__ in, double *__restrict__ out)
+{
+    __shared__ double sh[32 * 33];
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int nr = nfun[tile_row[t]], nc = nfun[tile_col[t]];
+        const double *src = in + tile_off[t];            // (i, j) at j * nr + i
+        double *dst = out + tile_off[trans[t]];          // (j, i) at i * nc + j
+        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+            const int j = e / nr, i = e - j * nr;
+            sh[i * 33 + j] = src[e];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+            const int i = e / nc, j = e - i * nc;
+            dst[e] = sh[i * 33 + j];
+        }
+        __syncthreads();
     }
 }
 
@@ -821,57 +827,87 @@ bool overlap(const void *a, const void *b, size_t bytes)
 
 namespace spm {
 
-int launch_gemm_grouped(spm_pattern p, const double *A, int ta, const double *B, int tb, double *C, hipStream_t s)
+int ilog2_ceil(int x)
+{
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+// C = P_S(A B^T) with the grouped kernel.
+int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, hipStream_t s)
 {
     GroupArgs g;
     g.grp_mem = p->d_grp_mem.ptr; g.grp_s = p->d_grp_s.ptr; g.grp_g = p->d_grp_g.ptr;
     g.unit_gr = p->d_unit_gr.ptr; g.unit_gc = p->d_unit_gc.ptr; g.unit_out = p->d_unit_out.ptr;
     g.unit_order = p->d_unit_order.ptr; g.pair_off = p->d_pair_off.ptr; g.pair_a = p->d_pair_a.ptr;
-    g.pair_b = p->d_pair_b.ptr; g.gl_nm = p->d_gl_nm.ptr; g.gl_offd = p->d_gl_offd.ptr; g.gl_offt = p->d_gl_offt.ptr;
+    g.pair_b = p->d_pair_b.ptr; g.gl_nm = p->d_gl_nm.ptr; g.gl_offd = p->d_gl_offd.ptr;
     g.stage_off = p->d_stage_off.ptr; g.stage_first = p->d_stage_first.ptr; g.tile_off = p->d_tile_off.ptr;
     g.nfun = p->d_nfun.ptr;
-    const int sel = (ta ? 2 : 0) + (tb ? 1 : 0);
     static bool attr_set = false;
     if (!attr_set) {
         const int mx = 160 * 1024;
-#define SPM_ATTR(W)                                                                                                       \
-    SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<0, 0, W>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));     \
-    SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<0, 1, W>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));     \
-    SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<1, 0, W>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));     \
-    SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<1, 1, W>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        SPM_ATTR(1) SPM_ATTR(8)
-#undef SPM_ATTR
+        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<1, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<8, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
         attr_set = true;
     }
+    const bool wide = p->all_even;   // two doubles per lane never straddle a cluster's functions
     for (const auto &L : p->launches) {
         g.first = L.first;
         g.count = L.count;
         g.RB = L.rb;
         g.CB = L.cb;
-        const int R = 16 * L.rb, Cc = 16 * L.cb, Rp = (R + 31) & ~31, Cp = (Cc + 31) & ~31;
-        // row-fast panels need the per k row records, which only 8-wave units build
-        g.akf = (ta == 1 || L.smax_r <= 8 || L.waves == 1) ? 1 : 0;
-        g.bkf = (tb == 0 || L.smax_c <= 8 || L.waves == 1) ? 1 : 0;
-        // the k-slice reduction (at most 7 x 4 x 64 doubles) fits in two buffers
-        g.panel_doubles = (g.akf ? R * kKF : kKS * Rp) + (g.bkf ? Cc * kKF : kKS * Cp);
-        const int waves = L.waves == 1 ? 1 : 8;
-        const int upw = waves == 1 ? 4 : 1;
-        const size_t lds = upw * (2 * (size_t)g.panel_doubles * sizeof(double) +
-                                  (waves == 8 ? unit_tab_bytes<8>() : unit_tab_bytes<1>()));
+        g.lxa = std::max(4, ilog2_ceil(16 * L.rb));
+        g.lxb = std::max(4, ilog2_ceil(16 * L.cb));
+        const size_t pd = (size_t)kKS * ((1 << g.lxa) + (1 << g.lxb));
+        // two operand buffers (they also hold the k-slice reduction, at most 7 x 4 x 64
+        // doubles) and two stage records
+        const size_t lds = 2 * pd * sizeof(double) + 2 * sizeof(KTab);
         if (lds > 160 * 1024) return fail(SPM_EUNSUPPORTED, "grouped product: LDS budget exceeded");
-        dim3 grid((unsigned)((L.count + upw - 1) / upw));
-#define SPM_LAUNCH_GRP(W)                                                                                   \
-    switch (sel) {                                                                                          \
-    case 0: hipLaunchKernelGGL((k_mgemm_grp<0, 0, W>), grid, dim3(W == 8 ? 512 : 256), lds, s, g, A, B, C); break;   \
-    case 1: hipLaunchKernelGGL((k_mgemm_grp<0, 1, W>), grid, dim3(W == 8 ? 512 : 256), lds, s, g, A, B, C); break;   \
-    case 2: hipLaunchKernelGGL((k_mgemm_grp<1, 0, W>), grid, dim3(W == 8 ? 512 : 256), lds, s, g, A, B, C); break;   \
-    default: hipLaunchKernelGGL((k_mgemm_grp<1, 1, W>), grid, dim3(W == 8 ? 512 : 256), lds, s, g, A, B, C); break;  \
-    }
-        if (waves == 1) { SPM_LAUNCH_GRP(1) } else { SPM_LAUNCH_GRP(8) }
-#undef SPM_LAUNCH_GRP
+        dim3 grid((unsigned)L.count);
+        if (L.waves == 1) {
+            if (wide) hipLaunchKernelGGL((k_mgemm_grp<1, 16>), grid, dim3(64), lds, s, g, A, B, C);
+            else hipLaunchKernelGGL((k_mgemm_grp<1, 4>), grid, dim3(64), lds, s, g, A, B, C);
+        } else {
+            if (wide) hipLaunchKernelGGL((k_mgemm_grp<8, 16>), grid, dim3(512), lds, s, g, A, B, C);
+            else hipLaunchKernelGGL((k_mgemm_grp<8, 4>), grid, dim3(512), lds, s, g, A, B, C);
+        }
     }
     SPM_HIP(hipGetLastError());
     return SPM_OK;
+}
+
+int launch_transpose(spm_pattern p, const double *in, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_transpose, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(256), 0, s, p->n_tiles,
+                       p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_trans.ptr, p->d_nfun.ptr, in, out);
+    SPM_HIP(hipGetLastError());
+    return SPM_OK;
+}
+
+// C = P_S(op(A) op(B)): the grouped kernel computes P_S(A' B'^T) with A' = op(A) and
+// B'^T = op(B), so A is transposed when op(A) = A^T and B when op(B) = B.  The
+// transposed copies live in stream-ordered temporary device memory.
+int launch_gemm_grouped(spm_pattern p, const double *A, int ta, const double *B, int tb, double *C, hipStream_t s)
+{
+    const size_t bytes = (size_t)p->n_stored * sizeof(double);
+    double *ta_buf = nullptr, *tb_buf = nullptr;
+    if (ta) SPM_HIP(hipMallocAsync((void **)&ta_buf, bytes, s));
+    if (!tb) {
+        if (hipMallocAsync((void **)&tb_buf, bytes, s) != hipSuccess) {
+            if (ta_buf) (void)hipFreeAsync(ta_buf, s);
+            return fail(SPM_ENOMEM, "masked product: temporary transpose buffer");
+        }
+    }
+    int st = SPM_OK;
+    if (ta) st = launch_transpose(p, A, ta_buf, s);
+    if (!st && !tb) st = launch_transpose(p, B, tb_buf, s);
+    if (!st) st = launch_gemm_abt(p, ta ? ta_buf : A, tb ? B : tb_buf, C, s);
+    if (ta_buf) (void)hipFreeAsync(ta_buf, s);
+    if (tb_buf) (void)hipFreeAsync(tb_buf, s);
+    return st;
 }
 
 int launch_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C, hipStream_t s)

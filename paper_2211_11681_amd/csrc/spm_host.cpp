@@ -436,6 +436,8 @@ void build_groups(spm_pattern_s *p)
     }
     const int ng = (int)p->grp_s.size();
     p->ng = ng;
+    p->all_even = true;
+    for (int q = 0; q < nc; ++q) p->all_even = p->all_even && (p->nfun[q] % 2 == 0);
     // union lists
     p->gl_rp.assign(ng + 1, 0);
     p->gl_mu.clear(); p->gl_tile.clear();
@@ -527,18 +529,15 @@ void build_groups(spm_pattern_s *p)
     }
     p->padded_macs = 0.0;
     for (double x : cost) p->padded_macs += x;
-    // per union entry: cluster size and the element offsets of the member tiles and their transposes
+    // per union entry: cluster size and the element offsets of the member tiles
     const int64_t ne = (int64_t)p->gl_mu.size();
     p->gl_nm.resize(ne);
     p->gl_offd.assign(ne * 4, -1);
-    p->gl_offt.assign(ne * 4, -1);
     for (int64_t e = 0; e < ne; ++e) {
         p->gl_nm[e] = p->nfun[p->gl_mu[e]];
         for (int k = 0; k < 4; ++k) {
             const int32_t t = p->gl_tile[e * 4 + k];
-            if (t < 0) continue;
-            p->gl_offd[e * 4 + k] = p->tile_off[t];
-            p->gl_offt[e * 4 + k] = p->tile_off[p->trans[t]];
+            if (t >= 0) p->gl_offd[e * 4 + k] = p->tile_off[t];
         }
     }
     // stages: consecutive middle clusters of a unit packed while their padded sizes sum to at most 32

@@ -78,7 +78,7 @@ struct spm_pattern_s {
     std::vector<int64_t> pair_off;    // units + 1: offsets of each unit's middle-cluster list
     std::vector<int32_t> pair_a, pair_b;   // union-list entries of mu in U(G_r) and U(G_c)
     std::vector<int32_t> gl_nm;       // functions of the cluster of each union entry
-    std::vector<int64_t> gl_offd, gl_offt;   // entries x 4: element offset of tile (member, mu) and of its transpose, -1 absent
+    std::vector<int64_t> gl_offd;            // entries x 4: element offset of tile (member, mu), -1 absent
     std::vector<int64_t> stage_off;   // units + 1: stages of each unit
     std::vector<int32_t> stage_first; // first pair of each stage, relative to the unit's pair_off
     struct Launch {
@@ -88,6 +88,7 @@ struct spm_pattern_s {
     };
     std::vector<Launch> launches;
     double padded_macs = 0.0;         // multiply-adds the grouped kernel issues (incl. padding)
+    bool all_even = false;            // every cluster owns an even number of functions
     // masked patterns only (entry-level upload)
     std::vector<int64_t> csr_rp;      // n + 1
     std::vector<int32_t> csr_col;
@@ -97,7 +98,7 @@ struct spm_pattern_s {
     spm::DevBuf<int32_t> d_nfun, d_tile_row, d_tile_col, d_trans, d_diag_tile, d_order;
     spm::DevBuf<int32_t> d_grp_mem, d_grp_s, d_grp_g, d_grp_R, d_gl_mu, d_gl_tile, d_unit_gr, d_unit_gc, d_unit_out,
         d_unit_order;
-    spm::DevBuf<int64_t> d_gl_rp, d_pair_off, d_gl_offd, d_gl_offt, d_stage_off;
+    spm::DevBuf<int64_t> d_gl_rp, d_pair_off, d_gl_offd, d_stage_off;
     spm::DevBuf<int32_t> d_pair_a, d_pair_b, d_gl_nm, d_stage_first;
     spm::DevBuf<uint8_t> d_keep;      // n_stored, masked patterns only
     spm::DevBuf<double> d_partial;    // reduction partials
