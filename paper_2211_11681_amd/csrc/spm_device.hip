@@ -1,6 +1,8 @@
 // Device side of libspm for gfx950: pattern upload, elementwise ops, deterministic
 // reductions, the masked product and the Newton-Schulz driver.
 #include <hip/hip_runtime.h>
+#include <mutex>
+#include <set>
 
 #include <algorithm>
 #include <cmath>
@@ -457,6 +459,7 @@ struct GroupArgs {
     int64_t first, count;
     int32_t RB, CB;
     int32_t lxa, lxb;        // log2 of the panel row strides
+    int32_t WR, WC, nsplit;  // wave grid over the blocks and number of k slices
 };
 
 constexpr int kKS = 32;   // k rows per stage
@@ -529,11 +532,23 @@ __device__ inline void gather_panel(const KTab *T, int slot_base, const double *
         const GatherLane g = gl[0];
         const int kstep = 1 << (LD - lx);
         const char *trow = reinterpret_cast<const char *>(&T->kofs[dl >> lx][slot_base + g.slot]);
-        for (int ins = wave; ins < nins; ins += WAVES) {
-            const int64_t o = *reinterpret_cast<const int64_t *>(trow + (size_t)ins * kstep * 64);
-            const double *src = (g.ok && o >= 0) ? M + o + g.i : zero;
-            lds_gather<WIDTH>(src, half, panel + ins * D);
+        const int rstride = kstep * 64 * WAVES;   // bytes between the records of consecutive instructions
+        for (int ins = wave; ins < nins; ins += 4 * WAVES) {
+            // four record reads in flight before the gathers that use them
+            int64_t o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int iq = ins + q * WAVES < nins ? ins + q * WAVES : ins;
+                o[q] = *reinterpret_cast<const int64_t *>(trow + (size_t)iq * kstep * 64);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (ins + q * WAVES >= nins) break;
+                const double *src = (g.ok && o[q] >= 0) ? M + o[q] + g.i : zero;
+                lds_gather<WIDTH>(src, half, panel + (ins + q * WAVES) * D);
+            }
         }
+        (void)rstride;
     } else {
         // D < X: variant v = ins % nv covers rows [v*D, v*D + D), k = ins / nv
         const int lnv = lx - LD, nv = 1 << lnv;
@@ -555,12 +570,11 @@ __device__ inline void gather_panel(const KTab *T, int slot_base, const double *
     }
 }
 
-template <int WAVES, int WIDTH>
+template <int WAVES, int WIDTH, int MR, int MC>
 __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const double *__restrict__ A,
                                                          const double *__restrict__ B, double *__restrict__ C)
 {
     extern __shared__ double lds[];
-    constexpr int MAXB = WAVES == 8 ? 8 : 1;       // accumulator blocks per wave
     constexpr int D = WIDTH * 8;                   // doubles per gather instruction
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = WAVES == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -582,12 +596,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     const int nc1 = ngc > 1 ? g.nfun[g.grp_mem[gc * 4 + 1]] : 0;
     const int nc2 = ngc > 2 ? g.nfun[g.grp_mem[gc * 4 + 2]] : 0;
     const int nc3 = ngc > 3 ? g.nfun[g.grp_mem[gc * 4 + 3]] : 0;
-    const int nblk = g.RB * g.CB;
-    const int nsplit = (WAVES == 1 || nblk >= WAVES) ? 1 : WAVES / nblk;
-    const int kslice = nsplit == 1 ? 0 : wave / nblk;
-    const bool active = WAVES == 1 || nblk >= WAVES || wave < nblk * nsplit;
-    const int b0 = (WAVES == 1 || nblk >= WAVES) ? wave : wave % nblk;
-    const int bstep = (WAVES == 8 && nblk >= WAVES) ? WAVES : 1 << 20;
+    // wave (wr, wc, kslice) owns the blocks (wr + i WR, wc + j WC), i < MR, j < MC, over
+    // the k rows of its slice
+    const int nw = g.WR * g.WC, nsplit = g.nsplit;
+    const bool active = wave < nw * nsplit;
+    const int wr = wave % g.WR, wc = (wave / g.WR) % g.WC, kslice = wave / nw;
     const int64_t s0 = g.stage_off[u], nst = g.stage_off[u + 1] - s0;
     const int64_t p0 = g.pair_off[u], npairs = g.pair_off[u + 1] - p0;
 
@@ -661,10 +674,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
         if (lane == 0) T->ks = kacc;
     };
 
-    dbl4 acc[MAXB];
+    dbl4 acc[MR][MC];
 #pragma unroll
-    for (int j = 0; j < MAXB; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < MR; ++i)
+#pragma unroll
+        for (int j = 0; j < MC; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
     const int lr = lane & 15, lk = lane >> 4;
+    int arow[MR], bcol[MC];                         // panel row offsets of the owned blocks (clamped)
+#pragma unroll
+    for (int i = 0; i < MR; ++i) arow[i] = 16 * min(wr + i * g.WR, g.RB - 1) + lr;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) bcol[j] = 16 * min(wc + j * g.WC, g.CB - 1) + lr;
 
     // prologue: records of stages 0 and 1 written; in registers: offsets of stage 2,
     // entries of stage 3, bounds of stage 4 (all loads complete at the first sync)
@@ -716,52 +736,79 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
             gather_panel<WAVES, WIDTH>(T1, 4, B, buf + kKS * Xa, ks_next, g.lxb, wave, dl, half, glb, zero);
         }
         if (active) {
+            // fragments of the next k step are read while the MFMAs of this one run
             const double *sA = lds + (s & 1) * pd, *sB = sA + kKS * Xa;
-            for (int k0 = 4 * kslice; k0 < ks_s; k0 += 4 * nsplit) {
-                const double *pa = sA + (k0 + lk) * Xa + lr;
-                const double *pb = sB + (k0 + lk) * Xb + lr;
+            int k0 = 4 * kslice;
+            double fa[MR], fb[MC];
 #pragma unroll
-                for (int j = 0; j < MAXB; ++j) {
-                    const int b = b0 + j * bstep;
-                    if (j == 0 || b < nblk) {
-                        const int rb = b / g.CB, cb = b - rb * g.CB;
-                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[16 * rb], pb[16 * cb], acc[j], 0, 0, 0);
-                    }
-                }
+            for (int i = 0; i < MR; ++i) fa[i] = sA[(k0 + lk) * Xa + arow[i]];
+#pragma unroll
+            for (int j = 0; j < MC; ++j) fb[j] = sB[(k0 + lk) * Xb + bcol[j]];
+            for (; k0 < ks_s; k0 += 4 * nsplit) {
+                const int kn = min(k0 + 4 * nsplit, kKS - 4) + lk;
+                double na[MR], nb[MC];
+#pragma unroll
+                for (int i = 0; i < MR; ++i) na[i] = sA[kn * Xa + arow[i]];
+#pragma unroll
+                for (int j = 0; j < MC; ++j) nb[j] = sB[kn * Xb + bcol[j]];
+#pragma unroll
+                for (int i = 0; i < MR; ++i)
+#pragma unroll
+                    for (int j = 0; j < MC; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < MR; ++i) fa[i] = na[i];
+#pragma unroll
+                for (int j = 0; j < MC; ++j) fb[j] = nb[j];
             }
         }
     }
     if (nsplit > 1) {                               // add the k slices in a fixed order
         unit_sync<WAVES>();
-        // waves nblk.. hold the partial sums of k slices 1..nsplit-1: slot (wave - nblk)
+        // waves nw.. hold the partial sums of k slices 1..nsplit-1: slot (wave - nw)
         if (active && kslice > 0)
-            for (int r = 0; r < 4; ++r) lds[(((wave - nblk) * 4) + r) * 64 + lane] = acc[0][r];
+#pragma unroll
+            for (int i = 0; i < MR; ++i)
+#pragma unroll
+                for (int j = 0; j < MC; ++j)
+                    for (int r = 0; r < 4; ++r)
+                        lds[((((wave - nw) * MR + i) * MC + j) * 4 + r) * 64 + lane] = acc[i][j][r];
         unit_sync<WAVES>();
         if (active && kslice == 0)
             for (int sl = 1; sl < nsplit; ++sl) {
-                const int w2 = sl * nblk + wave;
-                for (int r = 0; r < 4; ++r) acc[0][r] += lds[(((w2 - nblk) * 4) + r) * 64 + lane];
+                const int w2 = sl * nw + wave;
+#pragma unroll
+                for (int i = 0; i < MR; ++i)
+#pragma unroll
+                    for (int j = 0; j < MC; ++j)
+                        for (int r = 0; r < 4; ++r)
+                            acc[i][j][r] += lds[((((w2 - nw) * MR + i) * MC + j) * 4 + r) * 64 + lane];
             }
     }
     if (!active || kslice != 0) return;
     // store the output tiles that belong to S
 #pragma unroll
-    for (int j = 0; j < MAXB; ++j) {
-        const int b = b0 + j * bstep;
-        if (j > 0 && b >= nblk) continue;
-        const int rb = b / g.CB, cb = b - rb * g.CB;
-        const int col = 16 * cb + lr;
-        const int kc = col / sc, jj = col - kc * sc;
-        if (kc >= ngc || jj >= sel4(kc & 3, nc0, nc1, nc2, nc3)) continue;
-        const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
+    for (int i = 0; i < MR; ++i) {
+        const int rb = wr + i * g.WR;
+        if (rb >= g.RB) continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * rb + 4 * r + lk;
-            const int kr = row / sr, i = row - kr * sr;
-            if (kr >= ngr) continue;
-            const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
-            const int t = g.unit_out[u * 16 + kr * 4 + kc];
-            if (t >= 0 && i < nr) C[g.tile_off[t] + (int64_t)jj * nr + i] = acc[j][r];
+        for (int j = 0; j < MC; ++j) {
+            const int cb = wc + j * g.WC;
+            if (cb >= g.CB) continue;
+            const int col = 16 * cb + lr;
+            const int kc = col / sc, jj = col - kc * sc;
+            if (kc >= ngc) continue;
+            const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
+            if (jj >= ncl) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + 4 * r + lk;
+                const int kr = row / sr, ii = row - kr * sr;
+                if (kr >= ngr) continue;
+                const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
+                const int t = g.unit_out[u * 16 + kr * 4 + kc];
+                if (t >= 0 && ii < nr) C[g.tile_off[t] + (int64_t)jj * nr + ii] = acc[i][j][r];
+            }
         }
     }
 }
@@ -834,6 +881,27 @@ int ilog2_ceil(int x)
     return l;
 }
 
+// Launches one grouped-product kernel with `lds` bytes of dynamic LDS (the attribute
+// that allows more than 64 KiB is set on first use of each instantiation).
+int launch_grp(const void *k, dim3 grid, int threads, size_t lds, hipStream_t s, GroupArgs &g, const double *A,
+               const double *B, double *C)
+{
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> ready;   // (device, kernel)
+    int dev = 0;
+    SPM_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!ready.count({dev, k})) {
+            SPM_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+            ready.insert({dev, k});
+        }
+    }
+    void *args[] = {&g, &A, &B, &C};
+    SPM_HIP(hipLaunchKernel(k, grid, dim3(threads), args, lds, s));
+    return SPM_OK;
+}
+
 // C = P_S(A B^T) with the grouped kernel.
 int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, hipStream_t s)
 {
@@ -844,15 +912,6 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
     g.pair_b = p->d_pair_b.ptr; g.gl_nm = p->d_gl_nm.ptr; g.gl_offd = p->d_gl_offd.ptr;
     g.stage_off = p->d_stage_off.ptr; g.stage_first = p->d_stage_first.ptr; g.tile_off = p->d_tile_off.ptr;
     g.nfun = p->d_nfun.ptr;
-    static bool attr_set = false;
-    if (!attr_set) {
-        const int mx = 160 * 1024;
-        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<1, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        SPM_HIP(hipFuncSetAttribute((const void *)k_mgemm_grp<8, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        attr_set = true;
-    }
     const bool wide = p->all_even;   // two doubles per lane never straddle a cluster's functions
     for (const auto &L : p->launches) {
         g.first = L.first;
@@ -862,18 +921,44 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
         g.lxa = std::max(4, ilog2_ceil(16 * L.rb));
         g.lxb = std::max(4, ilog2_ceil(16 * L.cb));
         const size_t pd = (size_t)kKS * ((1 << g.lxa) + (1 << g.lxb));
-        // two operand buffers (they also hold the k-slice reduction, at most 7 x 4 x 64
-        // doubles) and two stage records
         const size_t lds = 2 * pd * sizeof(double) + 2 * sizeof(KTab);
         if (lds > 160 * 1024) return fail(SPM_EUNSUPPORTED, "grouped product: LDS budget exceeded");
-        dim3 grid((unsigned)L.count);
-        if (L.waves == 1) {
-            if (wide) hipLaunchKernelGGL((k_mgemm_grp<1, 16>), grid, dim3(64), lds, s, g, A, B, C);
-            else hipLaunchKernelGGL((k_mgemm_grp<1, 4>), grid, dim3(64), lds, s, g, A, B, C);
-        } else {
-            if (wide) hipLaunchKernelGGL((k_mgemm_grp<8, 16>), grid, dim3(512), lds, s, g, A, B, C);
-            else hipLaunchKernelGGL((k_mgemm_grp<8, 4>), grid, dim3(512), lds, s, g, A, B, C);
+        const dim3 grid((unsigned)L.count);
+        if (L.rb * L.cb == 1) {
+            g.WR = g.WC = g.nsplit = 1;
+            const void *k = wide ? (const void *)k_mgemm_grp<1, 16, 1, 1> : (const void *)k_mgemm_grp<1, 4, 1, 1>;
+            int st = launch_grp(k, grid, 64, lds, s, g, A, B, C);
+            if (st) return st;
+            continue;
         }
+        // wave patch MR x MC: fewest MFMAs per wave and k step, then fewest fragment reads
+        static const int shapes[8][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {1, 4}, {4, 1}, {2, 4}, {4, 2}};
+        int best = -1;
+        for (int q = 0; q < 8; ++q) {
+            const int mr = shapes[q][0], mc = shapes[q][1];
+            const int wr = (L.rb + mr - 1) / mr, wc = (L.cb + mc - 1) / mc;
+            if (wr * wc > 8) continue;
+            if (best < 0) { best = q; continue; }
+            const int bm = shapes[best][0] * shapes[best][1], qm = mr * mc;
+            const int bs = shapes[best][0] + shapes[best][1], qs = mr + mc;
+            if (qm < bm || (qm == bm && qs < bs)) best = q;
+        }
+        if (best < 0) return fail(SPM_EUNSUPPORTED, "grouped product: unit too large");
+        const int mr = shapes[best][0], mc = shapes[best][1];
+        g.WR = (L.rb + mr - 1) / mr;
+        g.WC = (L.cb + mc - 1) / mc;
+        g.nsplit = 8 / (g.WR * g.WC);
+        if ((size_t)(g.nsplit - 1) * g.WR * g.WC * mr * mc * 256 > 2 * pd)
+            return fail(SPM_EUNSUPPORTED, "grouped product: k-slice reduction exceeds LDS");
+        const void *k = nullptr;
+#define SPM_GRP_PICK(MR_, MC_)                                                                            \
+        if (mr == MR_ && mc == MC_)                                                                       \
+            k = wide ? (const void *)k_mgemm_grp<8, 16, MR_, MC_> : (const void *)k_mgemm_grp<8, 4, MR_, MC_>;
+        SPM_GRP_PICK(1, 1) SPM_GRP_PICK(1, 2) SPM_GRP_PICK(2, 1) SPM_GRP_PICK(2, 2)
+        SPM_GRP_PICK(1, 4) SPM_GRP_PICK(4, 1) SPM_GRP_PICK(2, 4) SPM_GRP_PICK(4, 2)
+#undef SPM_GRP_PICK
+        int st = launch_grp(k, grid, 512, lds, s, g, A, B, C);
+        if (st) return st;
     }
     SPM_HIP(hipGetLastError());
     return SPM_OK;
