@@ -12,9 +12,12 @@ One step = the whole hot path on one batch of input:
     Y = K + 0.1 I           (spm_axpy: copy of K, then the identity on the diagonal)
 
 Output: one JSON line.  value = pattern entries of C per second (whole job,
-inputs resident in HBM).  roofline: the product kernel's algorithmic FP64 flops
-(2 x the exact multiply-adds over the tile structure) per launch divided by its
-average duration from HIP events on the launch stream.
+inputs resident in HBM).  roofline: the product's algorithmic FP64 flops
+(2 x the exact multiply-adds over the tile structure, F in the roofline model)
+per call divided by its average duration from HIP events on the launch stream,
+against the dense FP64 MFMA peak; traffic = HBM bytes per call from the
+committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (null once the device code
+differs from the one the counters were taken on).
 """
 from __future__ import annotations
 
@@ -31,8 +34,9 @@ if ROOT not in sys.path:
 WORKLOAD = dict(workload="samplet_masked_product_cube3", n=131072, dim=3, kernel="matern_nu0.5", lengthscale=0.3,
                 vanishing_moments_degree=1, leaf=32, eta=1.0, seed=2)
 
-PEAK_FP64 = 78.6      # TFLOP/s, MI355X FP64 vector and matrix
+PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 matrix (and vector) peak
 PEAK_HBM = 8000.0     # GB/s
+TRAFFIC_SUMMARY = "masked_product_cube3_n131072_traffic.md"
 
 
 def parse():
@@ -43,15 +47,18 @@ def parse():
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy K once (n_stored doubles read and written) so that "
+                         "HBM counters can be scaled by a plain copy of known size")
     return ap.parse_args()
 
 
 def cpu_baseline(points, leaf, q, eta, threads):
     """Oracle's sorted-merge product timed on the host over a bounded row sample.
 
-    Sample: all basis rows of six clusters (three leaves at a quarter, half and
-    three quarters of the leaf order, and the middle clusters of the levels two,
-    four and six above the leaves); their output entries
+    Sample: all basis rows of 48 leaves spread evenly over the leaf order and of
+    the middle cluster of every internal level from level 4 down (the rows of
+    levels 0-3 are full and would dominate); their output entries
     c_ij = sum_{k in S_i cap S_j} a_ik b_kj are computed by the oracle's plain C
     merge with synthetic operand values (the pattern, not the values, sets the
     work)."""
@@ -65,12 +72,11 @@ def cpu_baseline(points, leaf, q, eta, threads):
     blocks = pattern.block_pattern(ot, eta)
     cs = ob.cluster_start
     n = int(cs[-1])
-    nf = np.diff(cs)
     leaves = np.nonzero(ot.sons[:, 0] < 0)[0]
     lv = ot.level
-    sample = [int(leaves[len(leaves) * k // 4]) for k in (1, 2, 3)]
-    for up in (2, 4, 6):
-        inner = np.nonzero(lv == max(0, ot.depth - up))[0]
+    sample = [int(leaves[(2 * k + 1) * len(leaves) // 96]) for k in range(48)]
+    for level in range(4, int(lv[leaves].min())):
+        inner = np.nonzero((lv == level) & (ot.sons[:, 0] >= 0))[0]
         sample.append(int(inner[len(inner) // 2]))
     need = sorted(set(np.concatenate([blocks[c] for c in sample]).tolist()) | set(sample))
     rowlen = np.zeros(n, np.int64)
@@ -89,14 +95,37 @@ def cpu_baseline(points, leaf, q, eta, threads):
     a = 2.0 * synth.pair_uniform(11, rows_i, col, n) - 1.0
     bt = 2.0 * synth.pair_uniform(12, col, rows_i, n) - 1.0      # bt[pos(j,k)] = b_kj
     rows = np.concatenate([np.arange(cs[c], cs[c + 1]) for c in sample])
-    os.environ["OMP_NUM_THREADS"] = str(threads)
+    used = native.set_threads(threads)
     t0 = time.perf_counter()
     _, cnt = native.masked_product_rows_bt(rows, rp, col, a, bt)
     dt = time.perf_counter() - t0
-    return {"value": cnt / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
-            "sample": f"all {len(rows)} basis rows of clusters {sample} (three leaves, three internal clusters at "
-                      f"levels {[int(lv[c]) for c in sample[3:]]}): {cnt} output entries of P_S(A B) by the oracle's "
-                      f"C sorted-merge product, synthetic operand values, {dt:.2f} s wall"}
+    return {"value": cnt / dt, "unit": "entries/s", "cores": used, "kind": "oracle",
+            "sample": f"all {len(rows)} basis rows of {len(sample)} clusters (48 leaves spread over the leaf "
+                      f"order, the middle cluster of internal levels {[int(lv[c]) for c in sample[48:]]}): {cnt} output "
+                      f"entries of P_S(A B) by the oracle's C sorted-merge product, synthetic operand values, "
+                      f"{dt:.2f} s wall on {used} threads"}
+
+
+def recorded_traffic():
+    """HBM bytes per product call from the committed rocprofv3 counter summary, or
+    None when the device code has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
+    src = os.path.join(ROOT, "paper_2211_11681_amd", "csrc", "spm_device.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("device_source_sha256") != digest:
+        return None
+    return float(fields["hbm_bytes_per_product"])
 
 
 def main():
@@ -153,11 +182,16 @@ def main():
     ms_total = start.elapsed_time(end)
     ms_step = ms_total / args.steps
     ms_gemm = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    if args.copy_calibration:
+        Kc = K.clone()
+        torch.cuda.synchronize()
+        del Kc
     print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, product {ms_gemm:.3f} ms", file=sys.stderr, flush=True)
 
     flops = 2.0 * pat.macs
     tflops = flops / (ms_gemm * 1e-3) / 1e12
     compulsory = 3 * pat.n_stored * 8          # A, B (here the same array, counted twice as operands) and C
+    traffic = recorded_traffic() if n == WORKLOAD["n"] else None
     out = {
         "metric": "pattern entries/s of P_S(A*B) (FP64), with HBM GB/s and FP32-split at stated relative error",
         "value": pat.nnz / (ms_step * 1e-3),
@@ -172,10 +206,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(w, n=n, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
-                     "frac": tflops / PEAK_FP64, "traffic": None},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": tflops / PEAK_FP64, "traffic": traffic},
         "product_ms": ms_gemm,
         "product_compulsory_GBps": compulsory / (ms_gemm * 1e-3) / 1e9,
+        "product_hbm_GBps": None if traffic is None else traffic / (ms_gemm * 1e-3) / 1e9,
         "setup_s": t_setup,
     }
     if not args.no_split:

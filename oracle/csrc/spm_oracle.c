@@ -12,6 +12,7 @@
  * Built with -ffp-contract=off so that every multiply and add rounds on its own.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -123,4 +124,18 @@ void oracle_kernel_apply(int64_t n, int d, const double *x, int64_t m, const dou
         }
         acc[q] = scale * s;
     }
+}
+
+/* OpenMP thread count for the calls above; returns the number of threads a
+ * parallel region then actually runs with. */
+int oracle_set_threads(int nthreads)
+{
+    int used = 0;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+    }
+    return used;
 }

@@ -39,8 +39,15 @@ def lib():
         L.oracle_kernel_apply.argtypes = [i64, ctypes.c_int, P, i64, P, P, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
         L.oracle_kernel_apply.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Sets the OpenMP thread count of the C helpers; returns the count a parallel region uses."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def _p(a: np.ndarray):
