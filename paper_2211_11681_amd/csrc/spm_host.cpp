@@ -574,27 +574,21 @@ void build_groups(spm_pattern_s *p)
             th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) pack(u, p->stage_first.data() + p->stage_off[u]); });
         for (auto &x : th) x.join();
     }
-    // launch classes by (row blocks, column blocks).  Inside a class the units that share
-    // the wider operand panel (rows of G_r when R >= C, else columns of G_c) run back to
-    // back on one XCD so that the panel's tiles are re-read from that XCD's L2:
-    // workgroups go to the 8 XCDs round robin, so the launch order interleaves eight
-    // lists, list x holding the units whose wide group g has g % 8 == x, ordered by g.
+    // Launch classes by (row blocks, column blocks).  Inside a class the units are cut
+    // into square blocks of b x b groups (group ids follow the cluster order, so a
+    // block is a spatially compact set of row and column groups); a block's units run
+    // back to back on one XCD, so the operand panels of its few row and column groups
+    // are re-read from that XCD's L2 instead of HBM.  b is the smallest power of two
+    // whose non-empty blocks hold on average at least as many units as one XCD runs
+    // at once.  Blocks go to the XCD with the least work so far, heaviest first, and
+    // inside a block the heaviest units start first.  Workgroups are dispatched to the
+    // 8 XCDs round robin, so the launch order interleaves the eight per-XCD lists.
+    auto key = [&](int64_t u) { return p->grp_R[p->unit_gr[u]] / 16 * 16 + p->grp_R[p->unit_gc[u]] / 16; };
     std::vector<int64_t> idx(nu);
     for (int64_t u = 0; u < nu; ++u) idx[u] = u;
-    auto key = [&](int64_t u) { return p->grp_R[p->unit_gr[u]] / 16 * 16 + p->grp_R[p->unit_gc[u]] / 16; };
-    auto wide = [&](int64_t u) {
-        return p->grp_R[p->unit_gr[u]] >= p->grp_R[p->unit_gc[u]] ? p->unit_gr[u] : p->unit_gc[u];
-    };
-    auto narrow = [&](int64_t u) {
-        return p->grp_R[p->unit_gr[u]] >= p->grp_R[p->unit_gc[u]] ? p->unit_gc[u] : p->unit_gr[u];
-    };
     std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
-        int kx = key(x), ky = key(y);
-        if (kx != ky) return kx < ky;
-        int wx = wide(x) % 8, wy = wide(y) % 8;
-        if (wx != wy) return wx < wy;
-        if (wide(x) != wide(y)) return wide(x) < wide(y);
-        return narrow(x) < narrow(y);
+        const int kx = key(x), ky = key(y);
+        return kx != ky ? kx < ky : x < y;
     });
     {
         std::vector<int64_t> out;
@@ -603,19 +597,69 @@ void build_groups(spm_pattern_s *p)
         while (c0 < nu) {
             int64_t c1 = c0;
             while (c1 < nu && key(idx[c1]) == key(idx[c0])) ++c1;
-            std::vector<int64_t> lo(9, c0);      // list x = idx[lo[x] .. lo[x+1])
-            for (int64_t i = c0; i < c1; ++i) lo[wide(idx[i]) % 8 + 1] = i + 1;
-            for (int x = 1; x <= 8; ++x) lo[x] = std::max(lo[x], lo[x - 1]);
-            std::vector<int64_t> pos(lo.begin(), lo.begin() + 8);
+            const int k = key(idx[c0]);
+            const int rb = k / 16, cb = k % 16;
+            // units one XCD holds at once: 32 CUs x workgroups per CU (LDS bound)
+            int per_cu = 7;
+            if (rb * cb > 1) {
+                int lxa = 4, lxb = 4;
+                while ((1 << lxa) < 16 * rb) ++lxa;
+                while ((1 << lxb) < 16 * cb) ++lxb;
+                const double lds = 2.0 * 32 * ((1 << lxa) + (1 << lxb)) * 8 + 4200;
+                per_cu = std::max(1, std::min(2, (int)(163840 / lds)));
+            }
+            const double target = 32.0 * per_cu;
+            int bsz = 1;
+            for (;; bsz *= 2) {
+                std::vector<int64_t> keys;
+                keys.reserve(c1 - c0);
+                for (int64_t i = c0; i < c1; ++i)
+                    keys.push_back((int64_t)(p->unit_gr[idx[i]] / bsz) * (1 << 20) + p->unit_gc[idx[i]] / bsz);
+                std::sort(keys.begin(), keys.end());
+                const int64_t nb = std::unique(keys.begin(), keys.end()) - keys.begin();
+                if ((double)(c1 - c0) / nb >= target || bsz >= (1 << 19)) break;
+            }
+            // blocks of the class
+            std::vector<std::pair<int64_t, int64_t>> bu;   // (block key, unit)
+            bu.reserve(c1 - c0);
+            for (int64_t i = c0; i < c1; ++i) {
+                const int64_t u = idx[i];
+                bu.push_back({(int64_t)(p->unit_gr[u] / bsz) * (1 << 20) + p->unit_gc[u] / bsz, u});
+            }
+            std::sort(bu.begin(), bu.end(), [&](const std::pair<int64_t, int64_t> &x, const std::pair<int64_t, int64_t> &y) {
+                if (x.first != y.first) return x.first < y.first;
+                if (cost[x.second] != cost[y.second]) return cost[x.second] > cost[y.second];
+                return x.second < y.second;
+            });
+            struct Blk { int64_t b0, b1; double w; };
+            std::vector<Blk> blks;
+            for (int64_t i = 0; i < (int64_t)bu.size();) {
+                int64_t j = i;
+                double w = 0.0;
+                while (j < (int64_t)bu.size() && bu[j].first == bu[i].first) w += cost[bu[j++].second];
+                blks.push_back({i, j, w});
+                i = j;
+            }
+            std::stable_sort(blks.begin(), blks.end(), [](const Blk &x, const Blk &y) { return x.w > y.w; });
+            std::vector<std::vector<int64_t>> lists(8);
+            double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (const auto &B : blks) {
+                int x = 0;
+                for (int y = 1; y < 8; ++y)
+                    if (load[y] < load[x]) x = y;
+                load[x] += B.w;
+                for (int64_t i = B.b0; i < B.b1; ++i) lists[x].push_back(bu[i].second);
+            }
+            std::vector<size_t> pos(8, 0);
             for (int64_t n = c0; n < c1; ++n) {
                 int x = (int)((n - c0) % 8);
-                if (pos[x] >= lo[x + 1]) {       // list exhausted: take from the longest remaining one
+                if (pos[x] >= lists[x].size()) {       // list exhausted: take from the longest remaining one
                     int best = 0;
                     for (int y = 1; y < 8; ++y)
-                        if (lo[y + 1] - pos[y] > lo[best + 1] - pos[best]) best = y;
+                        if (lists[y].size() - pos[y] > lists[best].size() - pos[best]) best = y;
                     x = best;
                 }
-                out.push_back(idx[pos[x]++]);
+                out.push_back(lists[x][pos[x]++]);
             }
             c0 = c1;
         }
