@@ -1,0 +1,102 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py times.
+
+Workload: N = 131072 points uniform in [0,1]^3 (seed 2), exponential kernel
+(Matern nu = 1/2) l = 0.3 scaled by 1/N, degree 1 (m = 4), leaf 32, eta = 1.0.
+The library builds tree, pattern and K^eta and computes C = P_S(K K) exactly as
+bench.py does.  The oracle computes, from the paper's definitions, the rows of
+K^Sigma = T K T^T for a sample of basis functions (three leaves and their
+ancestors on levels 10, 8, 6 and 4, two functions each) and from them every
+sampled entry c_ij = sum_{k in S_i cap S_j} K_ik K_jk with (i, j) in S.
+Sampled entries of K^eta and of C are compared one by one.
+
+Tolerance per entry: 1e-12 * ||K_i|| ||K_j|| for C (the Cauchy-Schwarz scale of
+the sum) and 1e-12 * ||K_i|| for K.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import compress, pattern, samplets, tree
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+N, D, SEED, LEAF, Q, ETA, P, ELL = 131072, 3, 2, 32, 1, 1.0, 0, 0.3
+
+
+def test_product_full_size_sampled_entries():
+    print("case: full-size product N=131072 cube3 leaf32 eta1.0 exponential l0.3", flush=True)
+    from paper_2211_11681_amd import spm
+    spm._lib.load()
+    assert torch.cuda.is_available()
+    pts = synth.points_cube(N, D, SEED)
+    t = spm.Tree(pts, LEAF, Q)
+    pat = spm.Pattern.from_tree(t, ETA)
+    K = spm.kernel_compress(pat, t, P, ELL, 1.0 / N)
+    C = spm.masked_gemm(pat, K, K)
+    torch.cuda.synchronize()
+    cs_lib = t.arrays()["cluster_start"]
+
+    # oracle construction
+    ot = tree.build_tree(pts, LEAF)
+    ob = samplets.build_samplets(ot, Q)
+    blocks = pattern.block_pattern(ot, ETA)
+    cs = ob.cluster_start
+    assert np.array_equal(cs, cs_lib)
+    nf = np.diff(cs)
+    leaves = np.nonzero(ot.sons[:, 0] < 0)[0]
+    parent = ot.parent
+    chosen = []
+    for li in (len(leaves) // 7, len(leaves) // 2, 5 * len(leaves) // 6):
+        c = int(leaves[li])
+        while c >= 0:
+            if c == leaves[li] or int(ot.level[c]) in (10, 8, 6, 4):
+                chosen.append(c)
+            c = parent[c]
+    rows = np.array(sorted({int(cs[c]) + k for c in set(chosen) for k in (0, int(nf[c]) - 1)}), np.int64)
+    clus_of = np.searchsorted(cs, rows, side="right") - 1
+    print(f"oracle rows: {len(rows)} from clusters {sorted(set(chosen))}", flush=True)
+    kr = compress.compress_rows(ob, rows, P, ELL, 1.0 / N, use_c=True)
+    masks = np.zeros((len(rows), N), bool)
+    for a, c in enumerate(clus_of):
+        for b in blocks[c]:
+            masks[a, cs[b]:cs[b + 1]] = True
+    keta = np.where(masks, kr, 0.0)
+    norms = np.linalg.norm(keta, axis=1)
+
+    # positions of (i, j) in the tile layout
+    tr, tc, to = pat.tiles()
+    nc = len(cs) - 1
+    tkey = tr.astype(np.int64) * nc + tc
+
+    def position(i, j):
+        ci = np.searchsorted(cs, i, side="right") - 1
+        cj = np.searchsorted(cs, j, side="right") - 1
+        t_ = np.searchsorted(tkey, ci * nc + cj)
+        assert tkey[t_] == ci * nc + cj
+        return to[t_] + (j - cs[cj]) * nf[ci] + (i - cs[ci])
+
+    # C entries: every sampled pair inside S
+    pairs = [(a, b) for a in range(len(rows)) for b in range(len(rows)) if masks[a, rows[b]]]
+    assert len(pairs) > 100
+    idx = torch.tensor([position(rows[a], rows[b]) for a, b in pairs], dtype=torch.int64, device="cuda")
+    got = C[idx].cpu().numpy()
+    ref = np.array([keta[a] @ keta[b] for a, b in pairs])
+    scale = np.array([norms[a] * norms[b] for a, b in pairs])
+    err = np.abs(got - ref) / scale
+    print(f"C: {len(pairs)} sampled entries, max error / (|K_i||K_j|) = {err.max():.3e}", flush=True)
+    assert err.max() < 1e-12
+
+    # K entries: 64 seeded columns of each sampled row
+    kpos, kref, kscale = [], [], []
+    for a, i in enumerate(rows):
+        cols = np.nonzero(masks[a])[0]
+        pick = cols[(synth.uniform(700 + a, np.arange(64)) * len(cols)).astype(np.int64)]
+        for j in pick:
+            kpos.append(position(i, j))
+            kref.append(keta[a, j])
+            kscale.append(norms[a])
+    gk = K[torch.tensor(kpos, dtype=torch.int64, device="cuda")].cpu().numpy()
+    kerr = np.abs(gk - np.array(kref)) / np.array(kscale)
+    print(f"K: {len(kpos)} sampled entries, max error / |K_i| = {kerr.max():.3e}", flush=True)
+    assert kerr.max() < 1e-12
