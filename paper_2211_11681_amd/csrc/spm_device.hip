@@ -527,7 +527,8 @@ __device__ inline void gather_panel(const KTab *T, int slot_base, const double *
     constexpr int LD = WIDTH == 16 ? 7 : 5;   // log2 D
     const int X = 1 << lx;
     const int nins = (ks * X + D - 1) >> LD;
-    if (lx <= LD) {
+    // with 16-byte lanes D = 128 >= X always (rows are at most 128 wide)
+    if (WIDTH == 16 || lx <= LD) {
         // D >= X: lane row x is fixed, k = ins * (D / X) + (dl >> lx)
         const GatherLane g = gl[0];
         const int kstep = 1 << (LD - lx);
@@ -549,7 +550,7 @@ __device__ inline void gather_panel(const KTab *T, int slot_base, const double *
             }
         }
         (void)rstride;
-    } else {
+    } else if constexpr (WIDTH != 16) {
         // D < X: variant v = ins % nv covers rows [v*D, v*D + D), k = ins / nv
         const int lnv = lx - LD, nv = 1 << lnv;
 #pragma unroll
@@ -601,8 +602,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     const int nw = g.WR * g.WC, nsplit = g.nsplit;
     const bool active = wave < nw * nsplit;
     const int wr = wave % g.WR, wc = (wave / g.WR) % g.WC, kslice = wave / nw;
-    const int64_t s0 = g.stage_off[u], nst = g.stage_off[u + 1] - s0;
-    const int64_t p0 = g.pair_off[u], npairs = g.pair_off[u + 1] - p0;
+    // per-unit bases, so that the stage loop keeps few uniform values live
+    const int64_t s0 = g.stage_off[u], p0 = g.pair_off[u];
+    const int nst = (int)(g.stage_off[u + 1] - s0), npairs = (int)(g.pair_off[u + 1] - p0);
+    const int32_t *const stf = g.stage_first + s0;
+    const int32_t *const ptab = (lane & 7) < 4 ? g.pair_a + p0 : g.pair_b + p0;   // this lane's list
 
     // per lane gather constants (variant v covers panel rows v*D .. v*D + D - 1 when D < X)
     const int dl = WIDTH == 16 ? 2 * lane : lane >> 1;
@@ -616,24 +620,30 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
         glb[v] = gather_lane(xb, sc, ngc, nc0, nc1, nc2, nc3);
     }
     const double *const zero = g_zero_word;
+    // member sizes of the record writer's slots (lanes 0..31 row members, 32..63 column)
+    int nslot[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nslot[q] = lane < 32 ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
 
-    // ---- stage records, fetched by wave 0 in three steps (bounds -> union entries ->
+    // ---- stage records, fetched by one wave in three steps (bounds -> union entries ->
     // offsets), one step per stage; each step only consumes loads of earlier stages, so
     // no stage waits for its own loads.  Lane (p, slot): middle cluster p of the stage,
     // slot 0..3 row members, 4..7 column members; slot 0 also carries the cluster size.
+    // the stage records are kept by a wave without MFMA blocks when there is one
+    const int twave = nw * nsplit < WAVES ? WAVES - 1 : 0;
     const int tp = lane >> 3, tslot = lane & 7, tk = tslot & 3;
     const bool tvalid = tslot < 4 ? tk < ngr : tk < ngc;
     // bounds of a stage: lane 0 loads its first union entry, lane 1 the end (per lane, so
     // that the value stays in a vector register and is only waited for at the next sync)
-    auto load_bounds = [&](int64_t st, int32_t &fbe) {
+    auto load_bounds = [&](int st, int32_t &fbe) {
         fbe = 0;
-        if (wave != 0 || st >= nst || lane > 1) return;
-        fbe = lane == 0 || st + 1 < nst ? g.stage_first[s0 + st + lane] : (int32_t)npairs;
+        if (wave != twave || st >= nst || lane > 1) return;
+        fbe = lane == 0 || st + 1 < nst ? stf[st + lane] : npairs;
     };
     auto load_entry = [&](int32_t fb, int np, int32_t &e) {
         e = -1;
-        if (wave != 0 || tp >= np) return;
-        e = tslot < 4 ? g.pair_a[p0 + fb + tp] : g.pair_b[p0 + fb + tp];
+        if (wave != twave || tp >= np) return;
+        e = ptab[fb + tp];
     };
     auto load_offsets = [&](int32_t e, int64_t &off, int32_t &nm) {
         off = -1;
@@ -643,7 +653,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
         if (tslot == 0) nm = g.gl_nm[e];
     };
     auto write_tab = [&](KTab *T, int64_t t_off, int t_nm, int t_np) {
-        if (wave != 0) return;
+        if (wave != twave) return;
         int nmv[kSP], kbv[kSP];
         int kacc = 0;
 #pragma unroll
@@ -668,7 +678,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t o = __shfl(t_off, mm * 8 + (rows ? 0 : 4) + q);
-            const int n = rows ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
+            const int n = nslot[q];
             T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * n : -1;
         }
         if (lane == 0) T->ks = kacc;
@@ -717,7 +727,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     // issued one iteration earlier), the record loads advance by one stage, the gathers
     // of stage s+1 are issued, then the MFMAs of stage s run.  Nothing issued in an
     // iteration is consumed before the sync that opens the next one.
-    for (int64_t s = 0; s < nst; ++s) {
+    for (int s = 0; s < nst; ++s) {
         unit_sync<WAVES>();                         // gathers of stage s landed; MFMAs of s-1 done
         const int ks_s = ks_next;
         const int np4 = np_of(fbe);
@@ -736,30 +746,52 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
             gather_panel<WAVES, WIDTH>(T1, 4, B, buf + kKS * Xa, ks_next, g.lxb, wave, dl, half, glb, zero);
         }
         if (active) {
-            // fragments of the next k step are read while the MFMAs of this one run
             const double *sA = lds + (s & 1) * pd, *sB = sA + kKS * Xa;
-            int k0 = 4 * kslice;
-            double fa[MR], fb[MC];
+            if constexpr (MR * MC <= 2) {
+                // small patches: the fragments of all (up to 8) k steps of the stage are
+                // read first, then the MFMAs issue back to back
+                double fa[8][MR], fb[8][MC];
 #pragma unroll
-            for (int i = 0; i < MR; ++i) fa[i] = sA[(k0 + lk) * Xa + arow[i]];
+                for (int t = 0; t < 8; ++t) {
+                    const int kr = min(4 * (kslice + t * nsplit), kKS - 4) + lk;
 #pragma unroll
-            for (int j = 0; j < MC; ++j) fb[j] = sB[(k0 + lk) * Xb + bcol[j]];
-            for (; k0 < ks_s; k0 += 4 * nsplit) {
-                const int kn = min(k0 + 4 * nsplit, kKS - 4) + lk;
-                double na[MR], nb[MC];
+                    for (int i = 0; i < MR; ++i) fa[t][i] = sA[kr * Xa + arow[i]];
 #pragma unroll
-                for (int i = 0; i < MR; ++i) na[i] = sA[kn * Xa + arow[i]];
+                    for (int j = 0; j < MC; ++j) fb[t][j] = sB[kr * Xb + bcol[j]];
+                }
 #pragma unroll
-                for (int j = 0; j < MC; ++j) nb[j] = sB[kn * Xb + bcol[j]];
+                for (int t = 0; t < 8; ++t)
+                    if (4 * (kslice + t * nsplit) < ks_s)
 #pragma unroll
-                for (int i = 0; i < MR; ++i)
+                        for (int i = 0; i < MR; ++i)
 #pragma unroll
-                    for (int j = 0; j < MC; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                            for (int j = 0; j < MC; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[t][i], fb[t][j], acc[i][j], 0, 0, 0);
+            } else {
+                // fragments of the next k step are read while the MFMAs of this one run
+                int k0 = 4 * kslice;
+                double fa[MR], fb[MC];
 #pragma unroll
-                for (int i = 0; i < MR; ++i) fa[i] = na[i];
+                for (int i = 0; i < MR; ++i) fa[i] = sA[(k0 + lk) * Xa + arow[i]];
 #pragma unroll
-                for (int j = 0; j < MC; ++j) fb[j] = nb[j];
+                for (int j = 0; j < MC; ++j) fb[j] = sB[(k0 + lk) * Xb + bcol[j]];
+                for (; k0 < ks_s; k0 += 4 * nsplit) {
+                    const int kn = min(k0 + 4 * nsplit, kKS - 4) + lk;
+                    double na[MR], nb[MC];
+#pragma unroll
+                    for (int i = 0; i < MR; ++i) na[i] = sA[kn * Xa + arow[i]];
+#pragma unroll
+                    for (int j = 0; j < MC; ++j) nb[j] = sB[kn * Xb + bcol[j]];
+#pragma unroll
+                    for (int i = 0; i < MR; ++i)
+#pragma unroll
+                        for (int j = 0; j < MC; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < MR; ++i) fa[i] = na[i];
+#pragma unroll
+                    for (int j = 0; j < MC; ++j) fb[j] = nb[j];
+                }
             }
         }
     }
@@ -786,7 +818,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
             }
     }
     if (!active || kslice != 0) return;
-    // store the output tiles that belong to S
+    // store the output tiles that belong to S (member sizes re-read here rather than
+    // kept live through the stage loop)
+    const int gr2 = g.unit_gr[u], gc2 = g.unit_gc[u];
+    const int sr2 = g.grp_s[gr2], sc2 = g.grp_s[gc2], ngr2 = g.grp_g[gr2], ngc2 = g.grp_g[gc2];
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
         const int rb = wr + i * g.WR;
@@ -796,16 +831,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
             const int cb = wc + j * g.WC;
             if (cb >= g.CB) continue;
             const int col = 16 * cb + lr;
-            const int kc = col / sc, jj = col - kc * sc;
-            if (kc >= ngc) continue;
-            const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
+            const int kc = col / sc2, jj = col - kc * sc2;
+            if (kc >= ngc2) continue;
+            const int ncl = g.nfun[g.grp_mem[gc2 * 4 + kc]];
             if (jj >= ncl) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * rb + 4 * r + lk;
-                const int kr = row / sr, ii = row - kr * sr;
-                if (kr >= ngr) continue;
-                const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
+                const int kr = row / sr2, ii = row - kr * sr2;
+                if (kr >= ngr2) continue;
+                const int nr = g.nfun[g.grp_mem[gr2 * 4 + kr]];
                 const int t = g.unit_out[u * 16 + kr * 4 + kc];
                 if (t >= 0 && ii < nr) C[g.tile_off[t] + (int64_t)jj * nr + ii] = acc[i][j][r];
             }
