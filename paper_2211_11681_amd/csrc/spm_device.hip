@@ -747,9 +747,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
         }
         if (active) {
             const double *sA = lds + (s & 1) * pd, *sB = sA + kKS * Xa;
-            if constexpr (MR * MC <= 2) {
-                // small patches: the fragments of all (up to 8) k steps of the stage are
-                // read first, then the MFMAs issue back to back
+            if constexpr (WAVES <= 2 || MR * MC <= 2 || MR + MC >= 8) {
+                // the fragments of all (up to 8) k steps of the stage are read first, then
+                // the MFMAs issue back to back (patches of 16 or fewer fragment registers
+                // per k step; the wide 1 x 7 patches run at one workgroup per CU and have
+                // the registers)
                 double fa[8][MR], fb[8][MC];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
@@ -960,21 +962,28 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
         if (lds > 160 * 1024) return fail(SPM_EUNSUPPORTED, "grouped product: LDS budget exceeded");
         const dim3 grid((unsigned)L.count);
         if (L.rb * L.cb == 1) {
+            // one 16 x 16 block: one MFMA wave plus a wave that keeps the stage records
             g.WR = g.WC = g.nsplit = 1;
-            const void *k = wide ? (const void *)k_mgemm_grp<1, 16, 1, 1> : (const void *)k_mgemm_grp<1, 4, 1, 1>;
-            int st = launch_grp(k, grid, 64, lds, s, g, A, B, C);
+            const void *k = wide ? (const void *)k_mgemm_grp<2, 16, 1, 1> : (const void *)k_mgemm_grp<2, 4, 1, 1>;
+            int st = launch_grp(k, grid, 128, lds, s, g, A, B, C);
             if (st) return st;
             continue;
         }
-        // wave patch MR x MC: fewest MFMAs per wave and k step, then fewest fragment reads
-        static const int shapes[8][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {1, 4}, {4, 1}, {2, 4}, {4, 2}};
+        // wave patch MR x MC: fewest MFMAs per SIMD and k step (8 waves on 4 SIMDs), then
+        // fewest fragment reads
+        static const int shapes[10][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {1, 4}, {4, 1}, {2, 4}, {4, 2}, {1, 7}, {7, 1}};
         int best = -1;
-        for (int q = 0; q < 8; ++q) {
+        auto simd_cost = [&](int q) {
+            const int mr = shapes[q][0], mc = shapes[q][1];
+            const int wr = (L.rb + mr - 1) / mr, wc = (L.cb + mc - 1) / mc;
+            return ((wr * wc + 3) / 4) * mr * mc;
+        };
+        for (int q = 0; q < 10; ++q) {
             const int mr = shapes[q][0], mc = shapes[q][1];
             const int wr = (L.rb + mr - 1) / mr, wc = (L.cb + mc - 1) / mc;
             if (wr * wc > 8) continue;
             if (best < 0) { best = q; continue; }
-            const int bm = shapes[best][0] * shapes[best][1], qm = mr * mc;
+            const int bm = simd_cost(best), qm = simd_cost(q);
             const int bs = shapes[best][0] + shapes[best][1], qs = mr + mc;
             if (qm < bm || (qm == bm && qs < bs)) best = q;
         }
@@ -991,6 +1000,7 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
             k = wide ? (const void *)k_mgemm_grp<8, 16, MR_, MC_> : (const void *)k_mgemm_grp<8, 4, MR_, MC_>;
         SPM_GRP_PICK(1, 1) SPM_GRP_PICK(1, 2) SPM_GRP_PICK(2, 1) SPM_GRP_PICK(2, 2)
         SPM_GRP_PICK(1, 4) SPM_GRP_PICK(4, 1) SPM_GRP_PICK(2, 4) SPM_GRP_PICK(4, 2)
+        SPM_GRP_PICK(1, 7) SPM_GRP_PICK(7, 1)
 #undef SPM_GRP_PICK
         int st = launch_grp(k, grid, 512, lds, s, g, A, B, C);
         if (st) return st;
