@@ -850,6 +850,202 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     }
 }
 
+// Thin units (one side a single 16-row block, at most 7 blocks): no LDS panels.
+// Wave b < nblk owns output block b and loads its MFMA fragments straight from the tile
+// layout into registers, one stage ahead (two register sets, the loop unrolled by two
+// so that the sets are static); the last wave keeps the stage records in a ring of
+// three LDS slots, two stages ahead.  Each stage ends with one barrier that waits for
+// LDS only, so fragment loads stay in flight across it.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vector memory may stay outstanding
+    __builtin_amdgcn_s_barrier();
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const double *__restrict__ A,
+                                                          const double *__restrict__ B, double *__restrict__ C)
+{
+    extern __shared__ double lds[];
+    KTab *ring = reinterpret_cast<KTab *>(lds);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t uidx = blockIdx.x;
+    if (uidx >= g.count) return;
+    const int u = g.unit_order[g.first + uidx];
+    const int gr = g.unit_gr[u], gc = g.unit_gc[u];
+    const int sr = g.grp_s[gr], sc = g.grp_s[gc];
+    const int ngr = g.grp_g[gr], ngc = g.grp_g[gc];
+    const int nr0 = g.nfun[g.grp_mem[gr * 4]];
+    const int nr1 = ngr > 1 ? g.nfun[g.grp_mem[gr * 4 + 1]] : 0;
+    const int nr2 = ngr > 2 ? g.nfun[g.grp_mem[gr * 4 + 2]] : 0;
+    const int nr3 = ngr > 3 ? g.nfun[g.grp_mem[gr * 4 + 3]] : 0;
+    const int nc0 = g.nfun[g.grp_mem[gc * 4]];
+    const int nc1 = ngc > 1 ? g.nfun[g.grp_mem[gc * 4 + 1]] : 0;
+    const int nc2 = ngc > 2 ? g.nfun[g.grp_mem[gc * 4 + 2]] : 0;
+    const int nc3 = ngc > 3 ? g.nfun[g.grp_mem[gc * 4 + 3]] : 0;
+    const int nblk = g.RB * g.CB;
+    const int producer = WAVES - 1;
+    const int64_t s0 = g.stage_off[u], p0 = g.pair_off[u];
+    const int nst = (int)(g.stage_off[u + 1] - s0), npairs = (int)(g.pair_off[u + 1] - p0);
+    const int lr = lane & 15, lk = lane >> 4;
+
+    if (wave == producer) {
+        // ---- stage records (same three-step fetch as the panel kernel)
+        const int32_t *const stf = g.stage_first + s0;
+        const int32_t *const ptab = (lane & 7) < 4 ? g.pair_a + p0 : g.pair_b + p0;
+        const int tp = lane >> 3, tslot = lane & 7, tk = tslot & 3;
+        const bool tvalid = tslot < 4 ? tk < ngr : tk < ngc;
+        int nslot[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nslot[q] = lane < 32 ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
+        auto load_bounds = [&](int st, int32_t &fbe) {
+            fbe = 0;
+            if (st >= nst || lane > 1) return;
+            fbe = lane == 0 || st + 1 < nst ? stf[st + lane] : npairs;
+        };
+        auto load_entry = [&](int32_t fb, int np, int32_t &e) {
+            e = -1;
+            if (tp >= np) return;
+            e = ptab[fb + tp];
+        };
+        auto load_offsets = [&](int32_t e, int64_t &off, int32_t &nm) {
+            off = -1;
+            nm = 0;
+            if (e < 0) return;
+            if (tvalid) off = g.gl_offd[(int64_t)e * 4 + tk];
+            if (tslot == 0) nm = g.gl_nm[e];
+        };
+        auto write_tab = [&](KTab *T, int64_t t_off, int t_nm, int t_np) {
+            int nmv[kSP], kbv[kSP];
+            int kacc = 0;
+#pragma unroll
+            for (int q = 0; q < kSP; ++q) {
+                nmv[q] = __shfl(t_nm, q * 8);
+                kbv[q] = kacc;
+                kacc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
+            }
+            const int kk = lane & 31;
+            const bool rows = lane < 32;
+            int m = -1;
+#pragma unroll
+            for (int q = 0; q < kSP; ++q)
+                if (q < t_np && kk >= kbv[q] && kk < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
+            const int mm = m < 0 ? 0 : m;
+            int nmm = 0, kbm = 0;
+#pragma unroll
+            for (int q = 0; q < kSP; ++q)
+                if (q == mm) { nmm = nmv[q]; kbm = kbv[q]; }
+            const int kkm = kk - kbm;
+            const bool live = m >= 0 && kkm < nmm;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t o = __shfl(t_off, mm * 8 + (rows ? 0 : 4) + q);
+                T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * nslot[q] : -1;
+            }
+            if (lane == 0) T->ks = kacc;
+        };
+        auto fb_of = [&](int32_t v) { return __builtin_amdgcn_readlane(v, 0); };
+        auto np_of = [&](int32_t v) { return __builtin_amdgcn_readlane(v, 1) - __builtin_amdgcn_readlane(v, 0); };
+        int32_t fbe, e, nm;
+        int64_t off;
+        for (int st = 0; st < 2; ++st) {
+            load_bounds(st, fbe);
+            load_entry(fb_of(fbe), np_of(fbe), e);
+            load_offsets(e, off, nm);
+            write_tab(&ring[st], off, nm, np_of(fbe));
+        }
+        load_bounds(2, fbe);
+        int np2 = np_of(fbe);
+        load_entry(fb_of(fbe), np2, e);
+        load_offsets(e, off, nm);                      // stage 2
+        load_bounds(3, fbe);
+        int np3 = np_of(fbe);
+        load_entry(fb_of(fbe), np3, e);                // stage 3
+        load_bounds(4, fbe);                           // stage 4
+        lds_barrier();
+        int slot = 2;                                  // ring slot of stage s + 2
+        for (int s = 0; s < nst; ++s) {
+            const int np4 = np_of(fbe);
+            const int32_t fb4 = fb_of(fbe);
+            write_tab(&ring[slot], off, nm, np2);      // stage s+2 (read by the consumers after this
+            load_offsets(e, off, nm);                  // stage's barrier, in iteration s+1)
+            load_entry(fb4, np4, e);
+            load_bounds(s + 5, fbe);
+            np2 = np3;
+            np3 = np4;
+            slot = slot == 2 ? 0 : slot + 1;
+            lds_barrier();
+        }
+        return;
+    }
+    if (wave >= nblk) {                                // no block: take part in the barriers only
+        lds_barrier();
+        for (int s = 0; s < nst; ++s) lds_barrier();
+        return;
+    }
+    // ---- consumer: block (rb, cb)
+    const int rb = g.RB == 1 ? 0 : wave, cb = g.RB == 1 ? wave : 0;
+    const int ra = 16 * rb + lr, kra = ra / sr, ia = ra - kra * sr;
+    const bool oka = kra < ngr && ia < sel4(kra & 3, nr0, nr1, nr2, nr3);
+    const int slota = kra & 3;
+    const int cbb = 16 * cb + lr, kcb = cbb / sc, jb = cbb - kcb * sc;
+    const bool okb = kcb < ngc && jb < sel4(kcb & 3, nc0, nc1, nc2, nc3);
+    const int slotb = 4 + (kcb & 3);
+    const double *const zero = g_zero_word;
+    auto load_stage = [&](const KTab *T, double (&fa)[8], double (&fb)[8]) {
+        const int ks = T->ks;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 4 * j + lk;
+            const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
+            const double *pa = (oka && oa >= 0) ? A + oa + ia : zero;
+            const double *pb = (okb && ob >= 0) ? B + ob + jb : zero;
+            fa[j] = *pa;
+            fb[j] = *pb;
+        }
+        return ks;
+    };
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    // rows at and past ks have no record (offset -1) and load zeros, so all eight k steps
+    // run unconditionally: straight-line code lets each MFMA wait for its own loads only
+    auto compute = [&](const double (&fa)[8], const double (&fb)[8], int ks) {
+        (void)ks;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j], fb[j], acc, 0, 0, 0);
+    };
+    double fa0[8], fb0[8], fa1[8], fb1[8];
+    lds_barrier();
+    int ks0 = nst > 0 ? load_stage(&ring[0], fa0, fb0) : 0, ks1 = 0;
+    int slot = 1;                                      // ring slot of stage s + 1
+    for (int s = 0; s < nst; s += 2) {
+        if (s + 1 < nst) ks1 = load_stage(&ring[slot], fa1, fb1);
+        slot = slot == 2 ? 0 : slot + 1;
+        compute(fa0, fb0, ks0);
+        lds_barrier();
+        if (s + 1 >= nst) break;
+        if (s + 2 < nst) ks0 = load_stage(&ring[slot], fa0, fb0);
+        slot = slot == 2 ? 0 : slot + 1;
+        compute(fa1, fb1, ks1);
+        lds_barrier();
+    }
+    // store the block where it belongs to S
+    const int col = 16 * cb + lr;
+    const int kc = col / sc, jj = col - kc * sc;
+    if (kc >= ngc) return;
+    const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
+    if (jj >= ncl) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rb + 4 * r + lk;
+        const int kr = row / sr, ii = row - kr * sr;
+        if (kr >= ngr) continue;
+        const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
+        const int t = g.unit_out[u * 16 + kr * 4 + kc];
+        if (t >= 0 && ii < nr) C[g.tile_off[t] + (int64_t)jj * nr + ii] = acc[r];
+    }
+}
+
 // Transpose of an S-matrix: tile (c, r) of X^T is (X_{r,c})^T.  One block per tile,
 // staged through LDS so that reads and writes are both contiguous.
 __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
@@ -961,6 +1157,17 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
         const size_t lds = 2 * pd * sizeof(double) + 2 * sizeof(KTab);
         if (lds > 160 * 1024) return fail(SPM_EUNSUPPORTED, "grouped product: LDS budget exceeded");
         const dim3 grid((unsigned)L.count);
+        if ((L.rb == 1 || L.cb == 1) && L.rb * L.cb <= 7) {
+            // one side a single block: register-direct kernel, one wave per block plus the
+            // record wave
+            g.WR = g.WC = g.nsplit = 1;
+            const size_t ring = 3 * sizeof(KTab);
+            int st;
+            if (L.rb * L.cb == 1) st = launch_grp((const void *)k_mgemm_thin<2>, grid, 128, ring, s, g, A, B, C);
+            else st = launch_grp((const void *)k_mgemm_thin<8>, grid, 512, ring, s, g, A, B, C);
+            if (st) return st;
+            continue;
+        }
         if (L.rb * L.cb == 1) {
             // one 16 x 16 block: one MFMA wave plus a wave that keeps the stage records
             g.WR = g.WC = g.nsplit = 1;
