@@ -891,7 +891,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     const int lr = lane & 15, lk = lane >> 4;
 
     if (wave == producer) {
-        // ---- stage records (same three-step fetch as the panel kernel)
+        // ---- stage records.  Record t (written two stages ahead, in iteration t - 2) needs
+        // three dependent loads: the stage bounds, the union entries of its middle clusters
+        // and their tile offsets.  Each step is issued kLag iterations before the next one
+        // uses it, so a load has kLag stages to arrive; every load is unconditional (clamped
+        // indices, results masked), which keeps the loop straight-line.  Lane (p, slot):
+        // middle cluster p of the stage, slot 0..3 row members, 4..7 column members.
+        constexpr int kLag = 4;
         const int32_t *const stf = g.stage_first + s0;
         const int32_t *const ptab = (lane & 7) < 4 ? g.pair_a + p0 : g.pair_b + p0;
         const int tp = lane >> 3, tslot = lane & 7, tk = tslot & 3;
@@ -899,24 +905,37 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
         int nslot[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) nslot[q] = lane < 32 ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
-        auto load_bounds = [&](int st, int32_t &fbe) {
-            fbe = 0;
-            if (st >= nst || lane > 1) return;
-            fbe = lane == 0 || st + 1 < nst ? stf[st + lane] : npairs;
+        // The loads of the loop go straight to LDS (one staging set per phase), so the
+        // wave waits for them explicitly: each phase issues exactly four load instructions
+        // (offsets 16 B and cluster size of the entries, entries, bounds), and at the start
+        // of a phase vmcnt <= 4 (kLag - 1) means the set loaded kLag phases ago has landed.
+        struct Staging {
+            int64_t off[128];                          // 16 bytes per lane, the first 8 used
+            int32_t nm[64], ent[64], bnd[64];
         };
-        auto load_entry = [&](int32_t fb, int np, int32_t &e) {
-            e = -1;
-            if (tp >= np) return;
-            e = ptab[fb + tp];
+        Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((3 * sizeof(KTab) + 15) & ~(size_t)15));
+        auto dma4 = [&](const void *src, void *dst) {
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
         };
-        auto load_offsets = [&](int32_t e, int64_t &off, int32_t &nm) {
-            off = -1;
-            nm = 0;
-            if (e < 0) return;
-            if (tvalid) off = g.gl_offd[(int64_t)e * 4 + tk];
-            if (tslot == 0) nm = g.gl_nm[e];
+        auto dma16 = [&](const void *src, void *dst) {
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
         };
-        auto write_tab = [&](KTab *T, int64_t t_off, int t_nm, int t_np) {
+        auto bound_ptr = [&](int t) { return stf + min(t + (lane & 1), nst - 1); };
+        auto fb_of = [&](int32_t raw) { return __builtin_amdgcn_readlane(raw, 0); };
+        auto np_of = [&](int32_t raw, int t) {
+            if (t >= nst) return 0;
+            const int end = t + 1 < nst ? __builtin_amdgcn_readlane(raw, 1) : npairs;
+            return end - __builtin_amdgcn_readlane(raw, 0);
+        };
+        auto entry_ptr = [&](int fb) { return ptab + max(0, min(fb + tp, npairs - 1)); };
+        auto issue_offsets = [&](int32_t e_raw, bool ok, Staging *P) {
+            const int32_t ec = ok ? e_raw : 0;
+            dma16(g.gl_offd + (int64_t)ec * 4 + tk, P->off);
+            dma4(g.gl_nm + ec, P->nm);
+        };
+        auto write_tab = [&](KTab *T, int64_t o_raw, int32_t m_raw, bool ok, int t_np) {
+            const int64_t t_off = (ok && tvalid) ? o_raw : -1;
+            const int t_nm = (ok && tslot == 0) ? m_raw : 0;
             int nmv[kSP], kbv[kSP];
             int kacc = 0;
 #pragma unroll
@@ -945,38 +964,69 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
             }
             if (lane == 0) T->ks = kacc;
         };
-        auto fb_of = [&](int32_t v) { return __builtin_amdgcn_readlane(v, 0); };
-        auto np_of = [&](int32_t v) { return __builtin_amdgcn_readlane(v, 1) - __builtin_amdgcn_readlane(v, 0); };
-        int32_t fbe, e, nm;
-        int64_t off;
-        for (int st = 0; st < 2; ++st) {
-            load_bounds(st, fbe);
-            load_entry(fb_of(fbe), np_of(fbe), e);
-            load_offsets(e, off, nm);
-            write_tab(&ring[st], off, nm, np_of(fbe));
+        // Staging set p serves the iterations s with s % kLag == p: it holds the offsets of
+        // stage s + 2, the entries of stage s + 2 + kLag and the bounds of stage
+        // s + 2 + 2 kLag; registers keep np(s + 2) (npw), np(s + 2 + kLag) (npo) and the
+        // validity of the lane's entry for both.
+        int32_t npw[kLag], npo[kLag];
+        bool oko[kLag], oke[kLag];
+        {
+            // prologue (waits allowed): records 0 and 1, then the loads of the four sets
+            int32_t bt[2 + 2 * kLag], et[2 + kLag];
+#pragma unroll
+            for (int t = 0; t < 2 + 2 * kLag; ++t) bt[t] = *bound_ptr(t);
+#pragma unroll
+            for (int t = 0; t < 2 + kLag; ++t) et[t] = *entry_ptr(fb_of(bt[t]));
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const bool ok = tp < np_of(bt[t], t);
+                const int32_t ec = ok ? et[t] : 0;
+                write_tab(&ring[t], g.gl_offd[(int64_t)ec * 4 + tk], g.gl_nm[ec], ok, np_of(bt[t], t));
+            }
+            __builtin_amdgcn_s_waitcnt(0);             // nothing of the prologue left in flight
+#pragma unroll
+            for (int q = 0; q < kLag; ++q) {
+                npw[q] = np_of(bt[q + 2], q + 2);
+                oko[q] = tp < npw[q];
+                issue_offsets(et[q + 2], oko[q], &stg[q]);
+                const int t2 = q + 2 + kLag;
+                npo[q] = np_of(bt[t2], t2);
+                oke[q] = tp < npo[q];
+                dma4(entry_ptr(fb_of(bt[t2])), stg[q].ent);
+                dma4(bound_ptr(q + 2 + 2 * kLag), stg[q].bnd);
+            }
         }
-        load_bounds(2, fbe);
-        int np2 = np_of(fbe);
-        load_entry(fb_of(fbe), np2, e);
-        load_offsets(e, off, nm);                      // stage 2
-        load_bounds(3, fbe);
-        int np3 = np_of(fbe);
-        load_entry(fb_of(fbe), np3, e);                // stage 3
-        load_bounds(4, fbe);                           // stage 4
         lds_barrier();
         int slot = 2;                                  // ring slot of stage s + 2
-        for (int s = 0; s < nst; ++s) {
-            const int np4 = np_of(fbe);
-            const int32_t fb4 = fb_of(fbe);
-            write_tab(&ring[slot], off, nm, np2);      // stage s+2 (read by the consumers after this
-            load_offsets(e, off, nm);                  // stage's barrier, in iteration s+1)
-            load_entry(fb4, np4, e);
-            load_bounds(s + 5, fbe);
-            np2 = np3;
-            np3 = np4;
+        auto phase = [&](int s, Staging *P, int32_t &nw, int32_t &no, bool &ko, bool &ke) {
+            __builtin_amdgcn_s_waitcnt(0x0F7C);        // vmcnt(12): this set's loads have landed
+            const int64_t o = P->off[2 * lane];
+            const int32_t m = P->nm[lane];
+            const int32_t er = P->ent[lane];
+            const int32_t br = P->bnd[lane];
+            write_tab(&ring[slot], o, m, ko, nw);      // stage s + 2
             slot = slot == 2 ? 0 : slot + 1;
+            issue_offsets(er, ke, P);                  // stage s + 2 + kLag
+            nw = no;
+            ko = ke;
+            const int t3 = s + 2 + 2 * kLag;
+            const int np3 = np_of(br, t3);
+            dma4(entry_ptr(fb_of(br)), P->ent);        // stage s + 2 + 2 kLag
+            no = np3;
+            ke = tp < np3;
+            dma4(bound_ptr(s + 2 + 3 * kLag), P->bnd); // stage s + 2 + 3 kLag
             lds_barrier();
+        };
+        for (int s = 0; s < nst; s += kLag) {
+            phase(s, &stg[0], npw[0], npo[0], oko[0], oke[0]);
+            if (s + 1 >= nst) break;
+            phase(s + 1, &stg[1], npw[1], npo[1], oko[1], oke[1]);
+            if (s + 2 >= nst) break;
+            phase(s + 2, &stg[2], npw[2], npo[2], oko[2], oke[2]);
+            if (s + 3 >= nst) break;
+            phase(s + 3, &stg[3], npw[3], npo[3], oko[3], oke[3]);
         }
+        __builtin_amdgcn_s_waitcnt(0);                 // let the last loads land before the wave ends
         return;
     }
     if (wave >= nblk) {                                // no block: take part in the barriers only
@@ -1161,7 +1211,8 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
             // one side a single block: register-direct kernel, one wave per block plus the
             // record wave
             g.WR = g.WC = g.nsplit = 1;
-            const size_t ring = 3 * sizeof(KTab);
+            // record ring, then (16-byte aligned) four staging sets of the record loads
+            const size_t ring = ((3 * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
             int st;
             if (L.rb * L.cb == 1) st = launch_grp((const void *)k_mgemm_thin<2>, grid, 128, ring, s, g, A, B, C);
             else st = launch_grp((const void *)k_mgemm_thin<8>, grid, 512, ring, s, g, A, B, C);

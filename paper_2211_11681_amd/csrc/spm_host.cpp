@@ -532,7 +532,7 @@ void build_groups(spm_pattern_s *p)
     // per union entry: cluster size and the element offsets of the member tiles
     const int64_t ne = (int64_t)p->gl_mu.size();
     p->gl_nm.resize(ne);
-    p->gl_offd.assign(ne * 4, -1);
+    p->gl_offd.assign(ne * 4 + 4, -1);   // padded: 16-byte reads of the last entry stay in bounds
     for (int64_t e = 0; e < ne; ++e) {
         p->gl_nm[e] = p->nfun[p->gl_mu[e]];
         for (int k = 0; k < 4; ++k) {
