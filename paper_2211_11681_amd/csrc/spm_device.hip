@@ -862,7 +862,16 @@ __device__ inline void lds_barrier()
     __builtin_amdgcn_s_barrier();
 }
 
-template <int WAVES>
+// Exchange of one double between adjacent lanes (2m <-> 2m + 1).
+__device__ inline double swap_adjacent(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);           // quad_perm 1,0,3,2
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0xB1, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int WAVES, bool PAIRED>
 __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const double *__restrict__ A,
                                                           const double *__restrict__ B, double *__restrict__ C)
 {
@@ -1043,16 +1052,39 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     const bool okb = kcb < ngc && jb < sel4(kcb & 3, nc0, nc1, nc2, nc3);
     const int slotb = 4 + (kcb & 3);
     const double *const zero = g_zero_word;
+    // PAIRED (every cluster size even): lanes 2m and 2m + 1 load the two rows (2m, 2m + 1)
+    // of one k column with one 16-byte load each, the even lane at k step j, the odd lane
+    // at k step j + 1, and swap one value, which halves the load instructions (the
+    // address unit bounds this kernel).
+    const bool odd = (lr & 1) != 0;
     auto load_stage = [&](const KTab *T, double (&fa)[8], double (&fb)[8]) {
         const int ks = T->ks;
+        if constexpr (PAIRED) {
+            typedef double dbl2 __attribute__((ext_vector_type(2)));
+            const int iap = odd ? ia - 1 : ia, jbp = odd ? jb - 1 : jb;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 4 * j + lk;
-            const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
-            const double *pa = (oka && oa >= 0) ? A + oa + ia : zero;
-            const double *pb = (okb && ob >= 0) ? B + ob + jb : zero;
-            fa[j] = *pa;
-            fb[j] = *pb;
+            for (int j = 0; j < 8; j += 2) {
+                const int k = 4 * (j + (odd ? 1 : 0)) + lk;
+                const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
+                const dbl2 va = *reinterpret_cast<const dbl2 *>((oka && oa >= 0) ? A + oa + iap : zero);
+                const dbl2 vb = *reinterpret_cast<const dbl2 *>((okb && ob >= 0) ? B + ob + jbp : zero);
+                const double xa = swap_adjacent(odd ? va.x : va.y);
+                const double xb = swap_adjacent(odd ? vb.x : vb.y);
+                fa[j] = odd ? xa : va.x;
+                fa[j + 1] = odd ? va.y : xa;
+                fb[j] = odd ? xb : vb.x;
+                fb[j + 1] = odd ? vb.y : xb;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 4 * j + lk;
+                const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
+                const double *pa = (oka && oa >= 0) ? A + oa + ia : zero;
+                const double *pb = (okb && ob >= 0) ? B + ob + jb : zero;
+                fa[j] = *pa;
+                fb[j] = *pb;
+            }
         }
         return ks;
     };
@@ -1214,8 +1246,10 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
             // record ring, then (16-byte aligned) four staging sets of the record loads
             const size_t ring = ((3 * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
             int st;
-            if (L.rb * L.cb == 1) st = launch_grp((const void *)k_mgemm_thin<2>, grid, 128, ring, s, g, A, B, C);
-            else st = launch_grp((const void *)k_mgemm_thin<8>, grid, 512, ring, s, g, A, B, C);
+            const void *k;
+            if (L.rb * L.cb == 1) k = wide ? (const void *)k_mgemm_thin<2, true> : (const void *)k_mgemm_thin<2, false>;
+            else k = wide ? (const void *)k_mgemm_thin<8, true> : (const void *)k_mgemm_thin<8, false>;
+            st = launch_grp(k, grid, L.rb * L.cb == 1 ? 128 : 512, ring, s, g, A, B, C);
             if (st) return st;
             continue;
         }
