@@ -108,11 +108,11 @@ def cpu_baseline(points, leaf, q, eta, threads):
 
 def recorded_traffic():
     """HBM bytes per product call from the committed rocprofv3 counter summary, or
-    None when the device code has changed since the counters were taken."""
+    None when the kernels or the schedule builder have changed since the counters
+    were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
-    src = os.path.join(ROOT, "paper_2211_11681_amd", "csrc", "spm_device.hip")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -121,9 +121,11 @@ def recorded_traffic():
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    if fields.get("device_source_sha256") != digest:
+    h = hashlib.sha256()
+    for name in ("spm_device.hip", "spm_host.cpp"):     # kernels and the schedule they run
+        with open(os.path.join(ROOT, "paper_2211_11681_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if fields.get("source_sha256") != h.hexdigest():
         return None
     return float(fields["hbm_bytes_per_product"])
 
