@@ -32,7 +32,12 @@
  *   SPM_F32SPLIT  float hi[n_stored] followed by float lo[n_stored]
  *                 (x = hi + lo, hi = fl32(x), lo = fl32(x - hi)); arithmetic in
  *                 FP32 with error-free products and compensated sums.
- *   SPM_F32ACC    float hi[n_stored]; FP32 products, compensated FP32 sums.
+ *   SPM_F32ACC    float hi[n_stored]; FP32 products.  The masked product sums
+ *                 them in FP32 over a stage (at most 32 summation indices)
+ *                 and adds the stage sums in FP64; tile classes the FP32
+ *                 matrix-core kernel does not cover (more than 7 blocks of
+ *                 16 rows on a side) use compensated FP32 sums instead.
+ *                 Results are rounded to FP32.
  */
 #ifndef SPM_H
 #define SPM_H

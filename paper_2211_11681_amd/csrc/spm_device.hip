@@ -871,6 +871,160 @@ __device__ inline double swap_adjacent(double x)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Record producer of the register-direct kernels (one wave, lane = this lane): keeps the
+// stage records of the unit in the three-slot ring `ring`, two stages ahead of the
+// consumers, with one LDS barrier per stage plus one after the prologue.  The four
+// staging sets of its record loads follow the ring in LDS.
+struct UnitInfo {
+    int64_t s0, p0;
+    int nst, npairs, ngr, ngc;
+    int nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3;
+};
+
+__device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *lds, KTab *ring, int lane)
+{
+    const int64_t s0 = ui.s0, p0 = ui.p0;
+    const int nst = ui.nst, npairs = ui.npairs, ngr = ui.ngr, ngc = ui.ngc;
+    const int nr0 = ui.nr0, nr1 = ui.nr1, nr2 = ui.nr2, nr3 = ui.nr3;
+    const int nc0 = ui.nc0, nc1 = ui.nc1, nc2 = ui.nc2, nc3 = ui.nc3;
+    // ---- stage records.  Record t (written two stages ahead, in iteration t - 2) needs
+    // three dependent loads: the stage bounds, the union entries of its middle clusters
+    // and their tile offsets.  Each step is issued kLag iterations before the next one
+    // uses it, so a load has kLag stages to arrive; every load is unconditional (clamped
+    // indices, results masked), which keeps the loop straight-line.  Lane (p, slot):
+    // middle cluster p of the stage, slot 0..3 row members, 4..7 column members.
+    constexpr int kLag = 4;
+    const int32_t *const stf = g.stage_first + s0;
+    const int32_t *const ptab = (lane & 7) < 4 ? g.pair_a + p0 : g.pair_b + p0;
+    const int tp = lane >> 3, tslot = lane & 7, tk = tslot & 3;
+    const bool tvalid = tslot < 4 ? tk < ngr : tk < ngc;
+    int nslot[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nslot[q] = lane < 32 ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
+    // The loads of the loop go straight to LDS (one staging set per phase), so the
+    // wave waits for them explicitly: each phase issues exactly four load instructions
+    // (offsets 16 B and cluster size of the entries, entries, bounds), and at the start
+    // of a phase vmcnt <= 4 (kLag - 1) means the set loaded kLag phases ago has landed.
+    struct Staging {
+        int64_t off[128];                          // 16 bytes per lane, the first 8 used
+        int32_t nm[64], ent[64], bnd[64];
+    };
+    Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((3 * sizeof(KTab) + 15) & ~(size_t)15));
+    auto dma4 = [&](const void *src, void *dst) {
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+    };
+    auto dma16 = [&](const void *src, void *dst) {
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    };
+    auto bound_ptr = [&](int t) { return stf + min(t + (lane & 1), nst - 1); };
+    auto fb_of = [&](int32_t raw) { return __builtin_amdgcn_readlane(raw, 0); };
+    auto np_of = [&](int32_t raw, int t) {
+        if (t >= nst) return 0;
+        const int end = t + 1 < nst ? __builtin_amdgcn_readlane(raw, 1) : npairs;
+        return end - __builtin_amdgcn_readlane(raw, 0);
+    };
+    auto entry_ptr = [&](int fb) { return ptab + max(0, min(fb + tp, npairs - 1)); };
+    auto issue_offsets = [&](int32_t e_raw, bool ok, Staging *P) {
+        const int32_t ec = ok ? e_raw : 0;
+        dma16(g.gl_offd + (int64_t)ec * 4 + tk, P->off);
+        dma4(g.gl_nm + ec, P->nm);
+    };
+    auto write_tab = [&](KTab *T, int64_t o_raw, int32_t m_raw, bool ok, int t_np) {
+        const int64_t t_off = (ok && tvalid) ? o_raw : -1;
+        const int t_nm = (ok && tslot == 0) ? m_raw : 0;
+        int nmv[kSP], kbv[kSP];
+        int kacc = 0;
+#pragma unroll
+        for (int q = 0; q < kSP; ++q) {
+            nmv[q] = __shfl(t_nm, q * 8);
+            kbv[q] = kacc;
+            kacc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
+        }
+        const int kk = lane & 31;
+        const bool rows = lane < 32;
+        int m = -1;
+#pragma unroll
+        for (int q = 0; q < kSP; ++q)
+            if (q < t_np && kk >= kbv[q] && kk < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
+        const int mm = m < 0 ? 0 : m;
+        int nmm = 0, kbm = 0;
+#pragma unroll
+        for (int q = 0; q < kSP; ++q)
+            if (q == mm) { nmm = nmv[q]; kbm = kbv[q]; }
+        const int kkm = kk - kbm;
+        const bool live = m >= 0 && kkm < nmm;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t o = __shfl(t_off, mm * 8 + (rows ? 0 : 4) + q);
+            T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * nslot[q] : -1;
+        }
+        if (lane == 0) T->ks = kacc;
+    };
+    // Staging set p serves the iterations s with s % kLag == p: it holds the offsets of
+    // stage s + 2, the entries of stage s + 2 + kLag and the bounds of stage
+    // s + 2 + 2 kLag; registers keep np(s + 2) (npw), np(s + 2 + kLag) (npo) and the
+    // validity of the lane's entry for both.
+    int32_t npw[kLag], npo[kLag];
+    bool oko[kLag], oke[kLag];
+    {
+        // prologue (waits allowed): records 0 and 1, then the loads of the four sets
+        int32_t bt[2 + 2 * kLag], et[2 + kLag];
+#pragma unroll
+        for (int t = 0; t < 2 + 2 * kLag; ++t) bt[t] = *bound_ptr(t);
+#pragma unroll
+        for (int t = 0; t < 2 + kLag; ++t) et[t] = *entry_ptr(fb_of(bt[t]));
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const bool ok = tp < np_of(bt[t], t);
+            const int32_t ec = ok ? et[t] : 0;
+            write_tab(&ring[t], g.gl_offd[(int64_t)ec * 4 + tk], g.gl_nm[ec], ok, np_of(bt[t], t));
+        }
+        __builtin_amdgcn_s_waitcnt(0);             // nothing of the prologue left in flight
+#pragma unroll
+        for (int q = 0; q < kLag; ++q) {
+            npw[q] = np_of(bt[q + 2], q + 2);
+            oko[q] = tp < npw[q];
+            issue_offsets(et[q + 2], oko[q], &stg[q]);
+            const int t2 = q + 2 + kLag;
+            npo[q] = np_of(bt[t2], t2);
+            oke[q] = tp < npo[q];
+            dma4(entry_ptr(fb_of(bt[t2])), stg[q].ent);
+            dma4(bound_ptr(q + 2 + 2 * kLag), stg[q].bnd);
+        }
+    }
+    lds_barrier();
+    int slot = 2;                                  // ring slot of stage s + 2
+    auto phase = [&](int s, Staging *P, int32_t &nw, int32_t &no, bool &ko, bool &ke) {
+        __builtin_amdgcn_s_waitcnt(0x0F7C);        // vmcnt(12): this set's loads have landed
+        const int64_t o = P->off[2 * lane];
+        const int32_t m = P->nm[lane];
+        const int32_t er = P->ent[lane];
+        const int32_t br = P->bnd[lane];
+        write_tab(&ring[slot], o, m, ko, nw);      // stage s + 2
+        slot = slot == 2 ? 0 : slot + 1;
+        issue_offsets(er, ke, P);                  // stage s + 2 + kLag
+        nw = no;
+        ko = ke;
+        const int t3 = s + 2 + 2 * kLag;
+        const int np3 = np_of(br, t3);
+        dma4(entry_ptr(fb_of(br)), P->ent);        // stage s + 2 + 2 kLag
+        no = np3;
+        ke = tp < np3;
+        dma4(bound_ptr(s + 2 + 3 * kLag), P->bnd); // stage s + 2 + 3 kLag
+        lds_barrier();
+    };
+    for (int s = 0; s < nst; s += kLag) {
+        phase(s, &stg[0], npw[0], npo[0], oko[0], oke[0]);
+        if (s + 1 >= nst) break;
+        phase(s + 1, &stg[1], npw[1], npo[1], oko[1], oke[1]);
+        if (s + 2 >= nst) break;
+        phase(s + 2, &stg[2], npw[2], npo[2], oko[2], oke[2]);
+        if (s + 3 >= nst) break;
+        phase(s + 3, &stg[3], npw[3], npo[3], oko[3], oke[3]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);                 // let the last loads land before the wave ends
+}
+
 template <int WAVES, bool PAIRED>
 __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const double *__restrict__ A,
                                                           const double *__restrict__ B, double *__restrict__ C)
@@ -900,142 +1054,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     const int lr = lane & 15, lk = lane >> 4;
 
     if (wave == producer) {
-        // ---- stage records.  Record t (written two stages ahead, in iteration t - 2) needs
-        // three dependent loads: the stage bounds, the union entries of its middle clusters
-        // and their tile offsets.  Each step is issued kLag iterations before the next one
-        // uses it, so a load has kLag stages to arrive; every load is unconditional (clamped
-        // indices, results masked), which keeps the loop straight-line.  Lane (p, slot):
-        // middle cluster p of the stage, slot 0..3 row members, 4..7 column members.
-        constexpr int kLag = 4;
-        const int32_t *const stf = g.stage_first + s0;
-        const int32_t *const ptab = (lane & 7) < 4 ? g.pair_a + p0 : g.pair_b + p0;
-        const int tp = lane >> 3, tslot = lane & 7, tk = tslot & 3;
-        const bool tvalid = tslot < 4 ? tk < ngr : tk < ngc;
-        int nslot[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nslot[q] = lane < 32 ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
-        // The loads of the loop go straight to LDS (one staging set per phase), so the
-        // wave waits for them explicitly: each phase issues exactly four load instructions
-        // (offsets 16 B and cluster size of the entries, entries, bounds), and at the start
-        // of a phase vmcnt <= 4 (kLag - 1) means the set loaded kLag phases ago has landed.
-        struct Staging {
-            int64_t off[128];                          // 16 bytes per lane, the first 8 used
-            int32_t nm[64], ent[64], bnd[64];
-        };
-        Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((3 * sizeof(KTab) + 15) & ~(size_t)15));
-        auto dma4 = [&](const void *src, void *dst) {
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
-        };
-        auto dma16 = [&](const void *src, void *dst) {
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
-        };
-        auto bound_ptr = [&](int t) { return stf + min(t + (lane & 1), nst - 1); };
-        auto fb_of = [&](int32_t raw) { return __builtin_amdgcn_readlane(raw, 0); };
-        auto np_of = [&](int32_t raw, int t) {
-            if (t >= nst) return 0;
-            const int end = t + 1 < nst ? __builtin_amdgcn_readlane(raw, 1) : npairs;
-            return end - __builtin_amdgcn_readlane(raw, 0);
-        };
-        auto entry_ptr = [&](int fb) { return ptab + max(0, min(fb + tp, npairs - 1)); };
-        auto issue_offsets = [&](int32_t e_raw, bool ok, Staging *P) {
-            const int32_t ec = ok ? e_raw : 0;
-            dma16(g.gl_offd + (int64_t)ec * 4 + tk, P->off);
-            dma4(g.gl_nm + ec, P->nm);
-        };
-        auto write_tab = [&](KTab *T, int64_t o_raw, int32_t m_raw, bool ok, int t_np) {
-            const int64_t t_off = (ok && tvalid) ? o_raw : -1;
-            const int t_nm = (ok && tslot == 0) ? m_raw : 0;
-            int nmv[kSP], kbv[kSP];
-            int kacc = 0;
-#pragma unroll
-            for (int q = 0; q < kSP; ++q) {
-                nmv[q] = __shfl(t_nm, q * 8);
-                kbv[q] = kacc;
-                kacc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
-            }
-            const int kk = lane & 31;
-            const bool rows = lane < 32;
-            int m = -1;
-#pragma unroll
-            for (int q = 0; q < kSP; ++q)
-                if (q < t_np && kk >= kbv[q] && kk < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
-            const int mm = m < 0 ? 0 : m;
-            int nmm = 0, kbm = 0;
-#pragma unroll
-            for (int q = 0; q < kSP; ++q)
-                if (q == mm) { nmm = nmv[q]; kbm = kbv[q]; }
-            const int kkm = kk - kbm;
-            const bool live = m >= 0 && kkm < nmm;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t o = __shfl(t_off, mm * 8 + (rows ? 0 : 4) + q);
-                T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * nslot[q] : -1;
-            }
-            if (lane == 0) T->ks = kacc;
-        };
-        // Staging set p serves the iterations s with s % kLag == p: it holds the offsets of
-        // stage s + 2, the entries of stage s + 2 + kLag and the bounds of stage
-        // s + 2 + 2 kLag; registers keep np(s + 2) (npw), np(s + 2 + kLag) (npo) and the
-        // validity of the lane's entry for both.
-        int32_t npw[kLag], npo[kLag];
-        bool oko[kLag], oke[kLag];
-        {
-            // prologue (waits allowed): records 0 and 1, then the loads of the four sets
-            int32_t bt[2 + 2 * kLag], et[2 + kLag];
-#pragma unroll
-            for (int t = 0; t < 2 + 2 * kLag; ++t) bt[t] = *bound_ptr(t);
-#pragma unroll
-            for (int t = 0; t < 2 + kLag; ++t) et[t] = *entry_ptr(fb_of(bt[t]));
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const bool ok = tp < np_of(bt[t], t);
-                const int32_t ec = ok ? et[t] : 0;
-                write_tab(&ring[t], g.gl_offd[(int64_t)ec * 4 + tk], g.gl_nm[ec], ok, np_of(bt[t], t));
-            }
-            __builtin_amdgcn_s_waitcnt(0);             // nothing of the prologue left in flight
-#pragma unroll
-            for (int q = 0; q < kLag; ++q) {
-                npw[q] = np_of(bt[q + 2], q + 2);
-                oko[q] = tp < npw[q];
-                issue_offsets(et[q + 2], oko[q], &stg[q]);
-                const int t2 = q + 2 + kLag;
-                npo[q] = np_of(bt[t2], t2);
-                oke[q] = tp < npo[q];
-                dma4(entry_ptr(fb_of(bt[t2])), stg[q].ent);
-                dma4(bound_ptr(q + 2 + 2 * kLag), stg[q].bnd);
-            }
-        }
-        lds_barrier();
-        int slot = 2;                                  // ring slot of stage s + 2
-        auto phase = [&](int s, Staging *P, int32_t &nw, int32_t &no, bool &ko, bool &ke) {
-            __builtin_amdgcn_s_waitcnt(0x0F7C);        // vmcnt(12): this set's loads have landed
-            const int64_t o = P->off[2 * lane];
-            const int32_t m = P->nm[lane];
-            const int32_t er = P->ent[lane];
-            const int32_t br = P->bnd[lane];
-            write_tab(&ring[slot], o, m, ko, nw);      // stage s + 2
-            slot = slot == 2 ? 0 : slot + 1;
-            issue_offsets(er, ke, P);                  // stage s + 2 + kLag
-            nw = no;
-            ko = ke;
-            const int t3 = s + 2 + 2 * kLag;
-            const int np3 = np_of(br, t3);
-            dma4(entry_ptr(fb_of(br)), P->ent);        // stage s + 2 + 2 kLag
-            no = np3;
-            ke = tp < np3;
-            dma4(bound_ptr(s + 2 + 3 * kLag), P->bnd); // stage s + 2 + 3 kLag
-            lds_barrier();
-        };
-        for (int s = 0; s < nst; s += kLag) {
-            phase(s, &stg[0], npw[0], npo[0], oko[0], oke[0]);
-            if (s + 1 >= nst) break;
-            phase(s + 1, &stg[1], npw[1], npo[1], oko[1], oke[1]);
-            if (s + 2 >= nst) break;
-            phase(s + 2, &stg[2], npw[2], npo[2], oko[2], oke[2]);
-            if (s + 3 >= nst) break;
-            phase(s + 3, &stg[3], npw[3], npo[3], oko[3], oke[3]);
-        }
-        __builtin_amdgcn_s_waitcnt(0);                 // let the last loads land before the wave ends
+        const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
+        record_producer(g, ui, lds, ring, lane);
         return;
     }
     if (wave >= nblk) {                                // no block: take part in the barriers only
@@ -1130,17 +1150,200 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
 
 // Transpose of an S-matrix: tile (c, r) of X^T is (X_{r,c})^T.  One block per tile,
 // staged through LDS so that reads and writes are both contiguous.
+// ---------------------------------------------------------------- FP32-accumulate product
+// F32ACC: the same unit schedule with FP32 operands and v_mfma_f32_16x16x4f32.  Each
+// stage's MFMA sums (FP32, 32 k rows) are added into FP64 accumulators; the result is
+// rounded to FP32 once.  Register-direct for every unit class: consumer wave w owns
+// block row w (all column blocks, MC >= CB) when the unit has several block rows, else
+// column block w; the last wave keeps the records.  QUAD (every cluster size a multiple
+// of 4): a 16-byte load gives rows 4m .. 4m+3 of one k column; lane 4m + q loads it at
+// k step j + q and a 4 x 4 transpose inside the lane quad gives each lane its own row
+// at the four k steps.
+__device__ inline float dpp_xor1(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, true));   // 1,0,3,2
+}
+
+__device__ inline float dpp_xor2(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, true));   // 2,3,0,1
+}
+
+// lane q of a quad holds v = M[q][0..3]; afterwards it holds M[0..3][q] (2 x 2 block
+// transposes at lane distance 1, then the exchange of the off-diagonal blocks at distance 2)
+__device__ inline void quad_transpose(float (&v)[4], int q)
+{
+    const bool b0 = (q & 1) != 0, b1 = (q & 2) != 0;
+    const float r0 = dpp_xor1(b0 ? v[0] : v[1]);
+    const float r1 = dpp_xor1(b0 ? v[2] : v[3]);
+    const float t0 = b0 ? r0 : v[0], t1 = b0 ? v[1] : r0;
+    const float t2 = b0 ? r1 : v[2], t3 = b0 ? v[3] : r1;
+    const float p0 = dpp_xor2(b1 ? t0 : t2);
+    const float p1 = dpp_xor2(b1 ? t1 : t3);
+    v[0] = b1 ? p0 : t0;
+    v[1] = b1 ? p1 : t1;
+    v[2] = b1 ? t2 : p0;
+    v[3] = b1 ? t3 : p1;
+}
+
+template <int WAVES, int MC, bool QUAD>
+__global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const float *__restrict__ A,
+                                                            const float *__restrict__ B, float *__restrict__ C)
+{
+    typedef float flt4 __attribute__((ext_vector_type(4)));
+    extern __shared__ double lds[];
+    KTab *ring = reinterpret_cast<KTab *>(lds);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t uidx = blockIdx.x;
+    if (uidx >= g.count) return;
+    const int u = g.unit_order[g.first + uidx];
+    const int gr = g.unit_gr[u], gc = g.unit_gc[u];
+    const int sr = g.grp_s[gr], sc = g.grp_s[gc];
+    const int ngr = g.grp_g[gr], ngc = g.grp_g[gc];
+    const int nr0 = g.nfun[g.grp_mem[gr * 4]];
+    const int nr1 = ngr > 1 ? g.nfun[g.grp_mem[gr * 4 + 1]] : 0;
+    const int nr2 = ngr > 2 ? g.nfun[g.grp_mem[gr * 4 + 2]] : 0;
+    const int nr3 = ngr > 3 ? g.nfun[g.grp_mem[gr * 4 + 3]] : 0;
+    const int nc0 = g.nfun[g.grp_mem[gc * 4]];
+    const int nc1 = ngc > 1 ? g.nfun[g.grp_mem[gc * 4 + 1]] : 0;
+    const int nc2 = ngc > 2 ? g.nfun[g.grp_mem[gc * 4 + 2]] : 0;
+    const int nc3 = ngc > 3 ? g.nfun[g.grp_mem[gc * 4 + 3]] : 0;
+    const bool rows_split = g.RB > 1;
+    const int nconsumer = rows_split ? g.RB : g.CB;
+    const int producer = WAVES - 1;
+    const int64_t s0 = g.stage_off[u], p0 = g.pair_off[u];
+    const int nst = (int)(g.stage_off[u + 1] - s0), npairs = (int)(g.pair_off[u + 1] - p0);
+    const int lr = lane & 15, lk = lane >> 4;
+
+    if (wave == producer) {
+        const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
+        record_producer(g, ui, lds, ring, lane);
+        return;
+    }
+    if (wave >= nconsumer) {
+        lds_barrier();
+        for (int s = 0; s < nst; ++s) lds_barrier();
+        return;
+    }
+    const int ncb = rows_split ? g.CB : 1;           // column blocks of this wave
+    const int rb = rows_split ? wave : 0;
+    const int ra = 16 * rb + lr, kra = ra / sr, ia = ra - kra * sr;
+    const bool oka = kra < ngr && ia < sel4(kra & 3, nr0, nr1, nr2, nr3);
+    const int slota = kra & 3;
+    int jb[MC], slotb[MC], cbv[MC];
+    bool okb[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+        cbv[c] = rows_split ? min(c, g.CB - 1) : wave;
+        const int col = 16 * cbv[c] + lr, kcb = col / sc;
+        jb[c] = col - kcb * sc;
+        okb[c] = kcb < ngc && jb[c] < sel4(kcb & 3, nc0, nc1, nc2, nc3);
+        slotb[c] = 4 + (kcb & 3);
+    }
+    const float *const zero = reinterpret_cast<const float *>(g_zero_word);
+    const int q = lr & 3;
+    // Fragments of half h (k steps 4h .. 4h + 3) of the stage whose record is T, kept as
+    // loaded (QUAD: rows 4m .. 4m + 3 at k step 4h + q) and put in MFMA order (the quad
+    // transpose) only when the half is computed, so no load is waited for when issued.
+    auto load_half = [&](const KTab *T, int h, flt4 &fa, flt4 (&fb)[MC]) {
+        if constexpr (QUAD) {
+            const int k = 4 * (4 * h + q) + lk;
+            const int64_t oa = T->kofs[k][slota];
+            fa = *reinterpret_cast<const flt4 *>((oka && oa >= 0) ? A + oa + (ia - q) : zero);
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int64_t ob = T->kofs[k][slotb[c]];
+                fb[c] = *reinterpret_cast<const flt4 *>((okb[c] && ob >= 0) ? B + ob + (jb[c] - q) : zero);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * (4 * h + t) + lk;
+                const int64_t oa = T->kofs[k][slota];
+                fa[t] = *((oka && oa >= 0) ? A + oa + ia : zero);
+#pragma unroll
+                for (int c = 0; c < MC; ++c) {
+                    const int64_t ob = T->kofs[k][slotb[c]];
+                    fb[c][t] = *((okb[c] && ob >= 0) ? B + ob + jb[c] : zero);
+                }
+            }
+        }
+    };
+    dbl4 acc[MC];
+    flt4 a32[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // rows at and past ks load zeros, so all k steps run unconditionally
+    auto compute_half = [&](const flt4 &fa_raw, const flt4 (&fb_raw)[MC]) {
+        float fa[4] = {fa_raw.x, fa_raw.y, fa_raw.z, fa_raw.w};
+        if constexpr (QUAD) quad_transpose(fa, q);
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            float fb[4] = {fb_raw[c].x, fb_raw[c].y, fb_raw[c].z, fb_raw[c].w};
+            if constexpr (QUAD) quad_transpose(fb, q);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a32[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[t], fb[t], a32[c], 0, 0, 0);
+        }
+    };
+    // Stage s: half 1 of s is loaded while half 0 runs, half 0 of s + 1 while half 1 runs;
+    // the stage's FP32 sums then go into the FP64 accumulators.
+    flt4 fax, fbx[MC], fay, fby[MC];
+    lds_barrier();
+    if (nst > 0) load_half(&ring[0], 0, fax, fbx);
+    int slot = 0;                                      // ring slot of stage s
+    for (int s = 0; s < nst; ++s) {
+        const int next = slot == 2 ? 0 : slot + 1;
+        load_half(&ring[slot], 1, fay, fby);
+        __builtin_amdgcn_sched_barrier(0);             // keep the loads ahead of the other half's compute
+#pragma unroll
+        for (int c = 0; c < MC; ++c) a32[c] = flt4{0.f, 0.f, 0.f, 0.f};
+        compute_half(fax, fbx);
+        __builtin_amdgcn_sched_barrier(0);
+        // unconditional: past the last stage the record has no rows and the loads read zeros
+        load_half(&ring[next], 0, fax, fbx);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_half(fay, fby);
+#pragma unroll
+        for (int c = 0; c < MC; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[c][r] += (double)a32[c][r];
+        slot = next;
+        lds_barrier();
+    }
+    // store the blocks where they belong to S
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+        if (c >= ncb) continue;
+        const int col = 16 * cbv[c] + lr;
+        const int kc = col / sc, jj = col - kc * sc;
+        if (kc >= ngc) continue;
+        const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
+        if (jj >= ncl) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rb + 4 * lk + r;    // FP32 MFMA: register r of lane l is row 4 (l / 16) + r
+            const int kr = row / sr, ii = row - kr * sr;
+            if (kr >= ngr) continue;
+            const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
+            const int t = g.unit_out[u * 16 + kr * 4 + kc];
+            if (t >= 0 && ii < nr) C[g.tile_off[t] + (int64_t)jj * nr + ii] = (float)acc[c][r];
+        }
+    }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
                                                    const int32_t *__restrict__ tile_row,
                                                    const int32_t *__restrict__ tile_col,
                                                    const int32_t *__restrict__ trans, const int32_t *__restrict__ nfun,
-                                                   const double *__restrict__ in, double *__restrict__ out)
+                                                   const T *__restrict__ in, T *__restrict__ out)
 {
-    __shared__ double sh[32 * 33];
+    __shared__ T sh[32 * 33];
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int nr = nfun[tile_row[t]], nc = nfun[tile_col[t]];
-        const double *src = in + tile_off[t];            // (i, j) at j * nr + i
-        double *dst = out + tile_off[trans[t]];          // (j, i) at i * nc + j
+        const T *src = in + tile_off[t];                 // (i, j) at j * nr + i
+        T *dst = out + tile_off[trans[t]];               // (j, i) at i * nc + j
         for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
             const int j = e / nr, i = e - j * nr;
             sh[i * 33 + j] = src[e];
@@ -1301,9 +1504,10 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
     return SPM_OK;
 }
 
-int launch_transpose(spm_pattern p, const double *in, double *out, hipStream_t s)
+template <typename T>
+int launch_transpose(spm_pattern p, const T *in, T *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_transpose, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(256), 0, s, p->n_tiles,
+    hipLaunchKernelGGL(k_transpose<T>, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(256), 0, s, p->n_tiles,
                        p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_trans.ptr, p->d_nfun.ptr, in, out);
     SPM_HIP(hipGetLastError());
     return SPM_OK;
@@ -1332,9 +1536,82 @@ int launch_gemm_grouped(spm_pattern p, const double *A, int ta, const double *B,
     return st;
 }
 
+// F32ACC: C = P_S(op(A) op(B)) with the register-direct FP32 kernel (unit classes of at
+// most 7 x 7 blocks; returns SPM_EUNSUPPORTED, before launching anything, otherwise).
+int launch_gemm_f32acc(spm_pattern p, const float *A, int ta, const float *B, int tb, float *C, hipStream_t s)
+{
+    for (const auto &L : p->launches)
+        if (L.rb > 7 || L.cb > 7) return SPM_EUNSUPPORTED;
+    const size_t bytes = (size_t)p->n_stored * sizeof(float);
+    float *ta_buf = nullptr, *tb_buf = nullptr;
+    if (ta) SPM_HIP(hipMallocAsync((void **)&ta_buf, bytes, s));
+    if (!tb && hipMallocAsync((void **)&tb_buf, bytes, s) != hipSuccess) {
+        if (ta_buf) (void)hipFreeAsync(ta_buf, s);
+        return fail(SPM_ENOMEM, "masked product: temporary transpose buffer");
+    }
+    int st = SPM_OK;
+    if (ta) st = launch_transpose(p, A, ta_buf, s);
+    if (!st && !tb) st = launch_transpose(p, B, tb_buf, s);
+    const float *Ap = ta ? ta_buf : A, *Bp = tb ? B : tb_buf;
+    GroupArgs g;
+    g.grp_mem = p->d_grp_mem.ptr; g.grp_s = p->d_grp_s.ptr; g.grp_g = p->d_grp_g.ptr;
+    g.unit_gr = p->d_unit_gr.ptr; g.unit_gc = p->d_unit_gc.ptr; g.unit_out = p->d_unit_out.ptr;
+    g.unit_order = p->d_unit_order.ptr; g.pair_off = p->d_pair_off.ptr; g.pair_a = p->d_pair_a.ptr;
+    g.pair_b = p->d_pair_b.ptr; g.gl_nm = p->d_gl_nm.ptr; g.gl_offd = p->d_gl_offd.ptr;
+    g.stage_off = p->d_stage_off.ptr; g.stage_first = p->d_stage_first.ptr; g.tile_off = p->d_tile_off.ptr;
+    g.nfun = p->d_nfun.ptr;
+    g.lxa = g.lxb = 4;
+    g.WR = g.WC = g.nsplit = 1;
+    const bool quad = p->all_mult4;
+    const size_t ring = ((3 * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
+    for (const auto &L : p->launches) {
+        if (st) break;
+        g.first = L.first;
+        g.count = L.count;
+        g.RB = L.rb;
+        g.CB = L.cb;
+        const dim3 grid((unsigned)L.count);
+        const void *k;
+        int threads = 512;
+        if (L.rb * L.cb == 1) {
+            k = quad ? (const void *)k_mgemm_f32acc<2, 1, true> : (const void *)k_mgemm_f32acc<2, 1, false>;
+            threads = 128;
+        } else if (L.rb == 1 || L.cb == 1) {
+            // one block per consumer wave (block rows or block columns)
+            k = quad ? (const void *)k_mgemm_f32acc<8, 1, true> : (const void *)k_mgemm_f32acc<8, 1, false>;
+        } else if (L.cb <= 2) {
+            k = quad ? (const void *)k_mgemm_f32acc<8, 2, true> : (const void *)k_mgemm_f32acc<8, 2, false>;
+        } else if (L.cb <= 4) {
+            k = quad ? (const void *)k_mgemm_f32acc<8, 4, true> : (const void *)k_mgemm_f32acc<8, 4, false>;
+        } else {
+            k = quad ? (const void *)k_mgemm_f32acc<8, 7, true> : (const void *)k_mgemm_f32acc<8, 7, false>;
+        }
+        // a unit of one block row (RB == 1) with several column blocks gives each wave one
+        // block; with several block rows each wave takes a row of blocks
+        if (L.rb == 1 && L.cb > 1) g.RB = 1;
+        st = launch_grp(k, grid, threads, ring, s, g, reinterpret_cast<const double *>(Ap),
+                        reinterpret_cast<const double *>(Bp), reinterpret_cast<double *>(C));
+    }
+    if (ta_buf) (void)hipFreeAsync(ta_buf, s);
+    if (tb_buf) (void)hipFreeAsync(tb_buf, s);
+    return st;
+}
+
 int launch_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C, hipStream_t s)
 {
     if (p->n_tiles == 0) return SPM_OK;
+    if (prec == SPM_F32ACC) {
+        int st = launch_gemm_f32acc(p, static_cast<const float *>(A), ta, static_cast<const float *>(B), tb,
+                                    static_cast<float *>(C), s);
+        if (st == SPM_OK) {
+            if (p->d_keep.ptr)
+                hipLaunchKernelGGL(k_apply_keep, dim3(grid1d(p->n_stored, 256)), dim3(256), 0, s, p->n_stored, prec,
+                                   p->d_keep.ptr, C);
+            SPM_HIP(hipGetLastError());
+            return SPM_OK;
+        }
+        if (st != SPM_EUNSUPPORTED) return st;       // classes wider than 7 blocks: per-tile kernel below
+    }
     if (prec == SPM_F64) {
         int st = launch_gemm_grouped(p, static_cast<const double *>(A), ta, static_cast<const double *>(B), tb,
                                      static_cast<double *>(C), s);

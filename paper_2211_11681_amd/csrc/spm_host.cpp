@@ -437,7 +437,11 @@ void build_groups(spm_pattern_s *p)
     const int ng = (int)p->grp_s.size();
     p->ng = ng;
     p->all_even = true;
-    for (int q = 0; q < nc; ++q) p->all_even = p->all_even && (p->nfun[q] % 2 == 0);
+    p->all_mult4 = true;
+    for (int q = 0; q < nc; ++q) {
+        p->all_even = p->all_even && (p->nfun[q] % 2 == 0);
+        p->all_mult4 = p->all_mult4 && (p->nfun[q] % 4 == 0);
+    }
     // union lists
     p->gl_rp.assign(ng + 1, 0);
     p->gl_mu.clear(); p->gl_tile.clear();

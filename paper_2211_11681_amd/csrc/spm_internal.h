@@ -89,6 +89,7 @@ struct spm_pattern_s {
     std::vector<Launch> launches;
     double padded_macs = 0.0;         // multiply-adds the grouped kernel issues (incl. padding)
     bool all_even = false;            // every cluster owns an even number of functions
+    bool all_mult4 = false;           // every cluster owns a multiple of 4 functions
     // masked patterns only (entry-level upload)
     std::vector<int64_t> csr_rp;      // n + 1
     std::vector<int32_t> csr_col;

@@ -123,10 +123,17 @@ def test_product_patterns_vs_oracle(S, kind, n, leaf, q, eta, seed):
     a[i, j] = 2 * synth.pair_uniform(31, i, j, n) - 1
     b[i, j] = 2 * synth.pair_uniform(32, i, j, n) - 1
     A, B = pat.values_from_csr(to_dev(a[mask])), pat.values_from_csr(to_dev(b[mask]))
+    A32 = {prec: S.convert(pat, A, "f64", prec) for prec in ("f32split", "f32acc")}
+    B32 = {prec: S.convert(pat, B, "f64", prec) for prec in ("f32split", "f32acc")}
     for ta, tb in [(0, 0), (0, 1), (1, 0), (1, 1)]:
         C = S.masked_gemm(pat, A, B, transA=bool(ta), transB=bool(tb))
         ref = ops.masked_product(a.T if ta else a, b.T if tb else b, mask)[mask]
         assert relerr(pat.values_to_csr(C).cpu().numpy(), ref) < TOL64, (ta, tb)
+        # FP32 modes on the same unit classes: F32SPLIT within 1e-8, F32ACC within 1e-6
+        for prec, tol in (("f32split", 1e-8), ("f32acc", 1e-6)):
+            C32 = S.masked_gemm(pat, A32[prec], B32[prec], transA=bool(ta), transB=bool(tb), prec=prec)
+            err = relerr(pat.values_to_csr(S.convert(pat, C32, prec, "f64")).cpu().numpy(), ref)
+            assert err <= tol, (prec, ta, tb, err)
 
 
 def test_product_identity_exact(S, cfg1):
