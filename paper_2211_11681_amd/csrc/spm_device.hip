@@ -872,22 +872,32 @@ __device__ inline double swap_adjacent(double x)
 }
 
 // Record producer of the register-direct kernels (one wave, lane = this lane): keeps the
-// stage records of the unit in the three-slot ring `ring`, two stages ahead of the
-// consumers, with one LDS barrier per stage plus one after the prologue.  The four
-// staging sets of its record loads follow the ring in LDS.
+// stage records of the unit in the ring `ring` of LEAD + 1 slots, LEAD stages ahead of
+// the consumers, with one LDS barrier per stage plus one after the prologue: before the
+// first barrier it writes records 0 .. LEAD - 1, and between barriers s and s + 1 record
+// s + LEAD, into the slot of record s - 1, which consumers no longer read once they may
+// read records up to s + LEAD - 1 in that interval.  The four staging sets of its record
+// loads follow the ring in LDS (ring_bytes<LEAD>() in all).
 struct UnitInfo {
     int64_t s0, p0;
     int nst, npairs, ngr, ngc;
     int nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3;
 };
 
+template <int LEAD>
+constexpr size_t ring_bytes()
+{
+    return (((LEAD + 1) * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
+}
+
+template <int LEAD>
 __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *lds, KTab *ring, int lane)
 {
     const int64_t s0 = ui.s0, p0 = ui.p0;
     const int nst = ui.nst, npairs = ui.npairs, ngr = ui.ngr, ngc = ui.ngc;
     const int nr0 = ui.nr0, nr1 = ui.nr1, nr2 = ui.nr2, nr3 = ui.nr3;
     const int nc0 = ui.nc0, nc1 = ui.nc1, nc2 = ui.nc2, nc3 = ui.nc3;
-    // ---- stage records.  Record t (written two stages ahead, in iteration t - 2) needs
+    // ---- stage records.  Record t (written LEAD stages ahead, in iteration t - LEAD) needs
     // three dependent loads: the stage bounds, the union entries of its middle clusters
     // and their tile offsets.  Each step is issued kLag iterations before the next one
     // uses it, so a load has kLag stages to arrive; every load is unconditional (clamped
@@ -909,7 +919,8 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         int64_t off[128];                          // 16 bytes per lane, the first 8 used
         int32_t nm[64], ent[64], bnd[64];
     };
-    Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((3 * sizeof(KTab) + 15) & ~(size_t)15));
+    constexpr int kSlots = LEAD + 1;
+    Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((kSlots * sizeof(KTab) + 15) & ~(size_t)15));
     auto dma4 = [&](const void *src, void *dst) {
         __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
     };
@@ -961,20 +972,20 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         if (lane == 0) T->ks = kacc;
     };
     // Staging set p serves the iterations s with s % kLag == p: it holds the offsets of
-    // stage s + 2, the entries of stage s + 2 + kLag and the bounds of stage
-    // s + 2 + 2 kLag; registers keep np(s + 2) (npw), np(s + 2 + kLag) (npo) and the
+    // stage s + LEAD, the entries of stage s + LEAD + kLag and the bounds of stage
+    // s + LEAD + 2 kLag; registers keep np(s + LEAD) (npw), np(s + LEAD + kLag) (npo) and the
     // validity of the lane's entry for both.
     int32_t npw[kLag], npo[kLag];
     bool oko[kLag], oke[kLag];
     {
-        // prologue (waits allowed): records 0 and 1, then the loads of the four sets
-        int32_t bt[2 + 2 * kLag], et[2 + kLag];
+        // prologue (waits allowed): records 0 .. LEAD - 1, then the loads of the four sets
+        int32_t bt[LEAD + 2 * kLag], et[LEAD + kLag];
 #pragma unroll
-        for (int t = 0; t < 2 + 2 * kLag; ++t) bt[t] = *bound_ptr(t);
+        for (int t = 0; t < LEAD + 2 * kLag; ++t) bt[t] = *bound_ptr(t);
 #pragma unroll
-        for (int t = 0; t < 2 + kLag; ++t) et[t] = *entry_ptr(fb_of(bt[t]));
+        for (int t = 0; t < LEAD + kLag; ++t) et[t] = *entry_ptr(fb_of(bt[t]));
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < LEAD; ++t) {
             const bool ok = tp < np_of(bt[t], t);
             const int32_t ec = ok ? et[t] : 0;
             write_tab(&ring[t], g.gl_offd[(int64_t)ec * 4 + tk], g.gl_nm[ec], ok, np_of(bt[t], t));
@@ -982,35 +993,35 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         __builtin_amdgcn_s_waitcnt(0);             // nothing of the prologue left in flight
 #pragma unroll
         for (int q = 0; q < kLag; ++q) {
-            npw[q] = np_of(bt[q + 2], q + 2);
+            npw[q] = np_of(bt[q + LEAD], q + LEAD);
             oko[q] = tp < npw[q];
-            issue_offsets(et[q + 2], oko[q], &stg[q]);
-            const int t2 = q + 2 + kLag;
+            issue_offsets(et[q + LEAD], oko[q], &stg[q]);
+            const int t2 = q + LEAD + kLag;
             npo[q] = np_of(bt[t2], t2);
             oke[q] = tp < npo[q];
             dma4(entry_ptr(fb_of(bt[t2])), stg[q].ent);
-            dma4(bound_ptr(q + 2 + 2 * kLag), stg[q].bnd);
+            dma4(bound_ptr(q + LEAD + 2 * kLag), stg[q].bnd);
         }
     }
     lds_barrier();
-    int slot = 2;                                  // ring slot of stage s + 2
+    int slot = LEAD;                               // ring slot of stage s + LEAD
     auto phase = [&](int s, Staging *P, int32_t &nw, int32_t &no, bool &ko, bool &ke) {
         __builtin_amdgcn_s_waitcnt(0x0F7C);        // vmcnt(12): this set's loads have landed
         const int64_t o = P->off[2 * lane];
         const int32_t m = P->nm[lane];
         const int32_t er = P->ent[lane];
         const int32_t br = P->bnd[lane];
-        write_tab(&ring[slot], o, m, ko, nw);      // stage s + 2
-        slot = slot == 2 ? 0 : slot + 1;
-        issue_offsets(er, ke, P);                  // stage s + 2 + kLag
+        write_tab(&ring[slot], o, m, ko, nw);      // stage s + LEAD
+        slot = slot == kSlots - 1 ? 0 : slot + 1;
+        issue_offsets(er, ke, P);                  // stage s + LEAD + kLag
         nw = no;
         ko = ke;
-        const int t3 = s + 2 + 2 * kLag;
+        const int t3 = s + LEAD + 2 * kLag;
         const int np3 = np_of(br, t3);
-        dma4(entry_ptr(fb_of(br)), P->ent);        // stage s + 2 + 2 kLag
+        dma4(entry_ptr(fb_of(br)), P->ent);        // stage s + LEAD + 2 kLag
         no = np3;
         ke = tp < np3;
-        dma4(bound_ptr(s + 2 + 3 * kLag), P->bnd); // stage s + 2 + 3 kLag
+        dma4(bound_ptr(s + LEAD + 3 * kLag), P->bnd); // stage s + LEAD + 3 kLag
         lds_barrier();
     };
     for (int s = 0; s < nst; s += kLag) {
@@ -1055,7 +1066,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
 
     if (wave == producer) {
         const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
-        record_producer(g, ui, lds, ring, lane);
+        record_producer<3>(g, ui, lds, ring, lane);
         return;
     }
     if (wave >= nblk) {                                // no block: take part in the barriers only
@@ -1072,63 +1083,78 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     const bool okb = kcb < ngc && jb < sel4(kcb & 3, nc0, nc1, nc2, nc3);
     const int slotb = 4 + (kcb & 3);
     const double *const zero = g_zero_word;
+    // A stage's 8 k steps are loaded in quarters of two steps, into a ring of eight
+    // register sets (two stages): a quarter is computed while the seven loaded after it
+    // are in flight, and its set is then refilled with the same quarter two stages on.
     // PAIRED (every cluster size even): lanes 2m and 2m + 1 load the two rows (2m, 2m + 1)
     // of one k column with one 16-byte load each, the even lane at k step j, the odd lane
-    // at k step j + 1, and swap one value, which halves the load instructions (the
-    // address unit bounds this kernel).
+    // at k step j + 1; one value is swapped between them when the quarter is computed.
+    // Without PAIRED a lane loads its own row at both steps.
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
     const bool odd = (lr & 1) != 0;
-    auto load_stage = [&](const KTab *T, double (&fa)[8], double (&fb)[8]) {
-        const int ks = T->ks;
+    const int iap = PAIRED && odd ? ia - 1 : ia, jbp = PAIRED && odd ? jb - 1 : jb;
+    auto load_q = [&](const KTab *T, int q, dbl2 &va, dbl2 &vb) {
         if constexpr (PAIRED) {
-            typedef double dbl2 __attribute__((ext_vector_type(2)));
-            const int iap = odd ? ia - 1 : ia, jbp = odd ? jb - 1 : jb;
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-                const int k = 4 * (j + (odd ? 1 : 0)) + lk;
-                const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
-                const dbl2 va = *reinterpret_cast<const dbl2 *>((oka && oa >= 0) ? A + oa + iap : zero);
-                const dbl2 vb = *reinterpret_cast<const dbl2 *>((okb && ob >= 0) ? B + ob + jbp : zero);
-                const double xa = swap_adjacent(odd ? va.x : va.y);
-                const double xb = swap_adjacent(odd ? vb.x : vb.y);
-                fa[j] = odd ? xa : va.x;
-                fa[j + 1] = odd ? va.y : xa;
-                fb[j] = odd ? xb : vb.x;
-                fb[j + 1] = odd ? vb.y : xb;
-            }
+            const int k = 4 * (2 * q + (odd ? 1 : 0)) + lk;
+            const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
+            va = *reinterpret_cast<const dbl2 *>((oka && oa >= 0) ? A + oa + iap : zero);
+            vb = *reinterpret_cast<const dbl2 *>((okb && ob >= 0) ? B + ob + jbp : zero);
         } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 4 * j + lk;
+            for (int h = 0; h < 2; ++h) {
+                const int k = 4 * (2 * q + h) + lk;
                 const int64_t oa = T->kofs[k][slota], ob = T->kofs[k][slotb];
-                const double *pa = (oka && oa >= 0) ? A + oa + ia : zero;
-                const double *pb = (okb && ob >= 0) ? B + ob + jb : zero;
-                fa[j] = *pa;
-                fb[j] = *pb;
+                va[h] = *((oka && oa >= 0) ? A + oa + ia : zero);
+                vb[h] = *((okb && ob >= 0) ? B + ob + jb : zero);
             }
         }
-        return ks;
     };
     dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-    // rows at and past ks have no record (offset -1) and load zeros, so all eight k steps
-    // run unconditionally: straight-line code lets each MFMA wait for its own loads only
-    auto compute = [&](const double (&fa)[8], const double (&fb)[8], int ks) {
-        (void)ks;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j], fb[j], acc, 0, 0, 0);
+    // rows at and past the stage's k count have no record (offset -1) and load zeros, so
+    // every k step runs unconditionally: straight-line code lets each MFMA wait for its
+    // own loads only
+    auto comp_q = [&](const dbl2 &va, const dbl2 &vb) {
+        double a0 = va.x, a1 = va.y, b0 = vb.x, b1 = vb.y;
+        if constexpr (PAIRED) {
+            const double xa = swap_adjacent(odd ? va.x : va.y);
+            const double xb = swap_adjacent(odd ? vb.x : vb.y);
+            a0 = odd ? xa : va.x;
+            a1 = odd ? va.y : xa;
+            b0 = odd ? xb : vb.x;
+            b1 = odd ? vb.y : xb;
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
     };
-    double fa0[8], fb0[8], fa1[8], fb1[8];
+    dbl2 qa[8], qb[8];
     lds_barrier();
-    int ks0 = nst > 0 ? load_stage(&ring[0], fa0, fb0) : 0, ks1 = 0;
-    int slot = 1;                                      // ring slot of stage s + 1
+    // (issued in ring order: the loop's waits count on set 0 being the oldest)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        load_q(&ring[q >> 2], q & 3, qa[q], qb[q]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // stage s is in sets 4 (s & 1) .. 4 (s & 1) + 3; past the last stage the records have
+    // no rows, so the refills are unconditional and load zeros.  Units have an even
+    // number of stages, so the loop body (two stages) has no exit in its middle, which
+    // would make the compiler wait for loads at the loop head that are still in flight.
+    int slot = 2;                                      // ring slot of stage s + 2
     for (int s = 0; s < nst; s += 2) {
-        if (s + 1 < nst) ks1 = load_stage(&ring[slot], fa1, fb1);
-        slot = slot == 2 ? 0 : slot + 1;
-        compute(fa0, fb0, ks0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            comp_q(qa[q], qb[q]);
+            load_q(&ring[slot], q, qa[q], qb[q]);
+            __builtin_amdgcn_sched_barrier(0);     // a quarter's swaps must not move ahead
+        }
+        slot = (slot + 1) & 3;
         lds_barrier();
-        if (s + 1 >= nst) break;
-        if (s + 2 < nst) ks0 = load_stage(&ring[slot], fa0, fb0);
-        slot = slot == 2 ? 0 : slot + 1;
-        compute(fa1, fb1, ks1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            comp_q(qa[4 + q], qb[4 + q]);
+            load_q(&ring[slot], q, qa[4 + q], qb[4 + q]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        slot = (slot + 1) & 3;
         lds_barrier();
     }
     // store the block where it belongs to S
@@ -1218,7 +1244,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
 
     if (wave == producer) {
         const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
-        record_producer(g, ui, lds, ring, lane);
+        record_producer<2>(g, ui, lds, ring, lane);
         return;
     }
     if (wave >= nconsumer) {
@@ -1446,8 +1472,7 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
             // one side a single block: register-direct kernel, one wave per block plus the
             // record wave
             g.WR = g.WC = g.nsplit = 1;
-            // record ring, then (16-byte aligned) four staging sets of the record loads
-            const size_t ring = ((3 * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
+            const size_t ring = ring_bytes<3>();
             int st;
             const void *k;
             if (L.rb * L.cb == 1) k = wide ? (const void *)k_mgemm_thin<2, true> : (const void *)k_mgemm_thin<2, false>;
@@ -1563,7 +1588,7 @@ int launch_gemm_f32acc(spm_pattern p, const float *A, int ta, const float *B, in
     g.lxa = g.lxb = 4;
     g.WR = g.WC = g.nsplit = 1;
     const bool quad = p->all_mult4;
-    const size_t ring = ((3 * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
+    const size_t ring = ring_bytes<2>();
     for (const auto &L : p->launches) {
         if (st) break;
         g.first = L.first;

@@ -561,6 +561,12 @@ void build_groups(spm_pattern_s *p)
             kacc += km;
             ++np;
         }
+        // an even stage count: the register-direct kernels run two stages per loop trip
+        // with a single exit; the extra stage is empty (it starts at the end of the list)
+        if (ns & 1) {
+            if (out) out[ns] = (int32_t)(f1 - f0);
+            ++ns;
+        }
         nst[u] = ns;
     };
     {
