@@ -890,8 +890,23 @@ constexpr size_t ring_bytes()
     return (((LEAD + 1) * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
 }
 
-template <int LEAD>
-__device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *lds, KTab *ring, int lane)
+// The fragment that every consumer wave of a unit needs (the unit's single 16-row side),
+// which the record wave copies into LDS once instead: per stage four quarters of 64 lanes
+// x 16 bytes, lane L holding what consumer lane L would load itself (the rows 2m, 2m + 1
+// of one k column, at k step 2q for even and 2q + 1 for odd lanes).  The copy of stage t
+// goes into slot t of a ring of as many slots as the record ring.
+struct SharedSide {
+    const double *X;     // operand of the shared side
+    double *dst;         // LDS ring, 512 doubles per slot
+    int slot;            // record column of the lane's member
+    int ipair;           // offset of the lane's row pair inside a tile column
+    int kodd;            // 1 on odd lanes
+    bool ok;             // the lane's row exists
+};
+
+template <int LEAD, bool SHARE>
+__device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *lds, KTab *ring, int lane,
+                                const SharedSide &sh)
 {
     const int64_t s0 = ui.s0, p0 = ui.p0;
     const int nst = ui.nst, npairs = ui.npairs, ngr = ui.ngr, ngc = ui.ngc;
@@ -913,8 +928,12 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
     for (int q = 0; q < 4; ++q) nslot[q] = lane < 32 ? sel4(q, nr0, nr1, nr2, nr3) : sel4(q, nc0, nc1, nc2, nc3);
     // The loads of the loop go straight to LDS (one staging set per phase), so the
     // wave waits for them explicitly: each phase issues exactly four load instructions
-    // (offsets 16 B and cluster size of the entries, entries, bounds), and at the start
-    // of a phase vmcnt <= 4 (kLag - 1) means the set loaded kLag phases ago has landed.
+    // (offsets 16 B and cluster size of the entries, entries, bounds), after the four
+    // shared-fragment copies with SHARE, and at the start of a phase vmcnt <= 4 (kLag - 1)
+    // (8 (kLag - 1) with SHARE) means the set loaded kLag phases ago has landed.  A copy
+    // for stage t is issued in phase t - LEAD, so it has landed at the start of phase
+    // t - LEAD + kLag and is visible to the consumers from barrier t - LEAD + kLag + 1 on,
+    // no later than barrier t when LEAD >= kLag + 1.
     struct Staging {
         int64_t off[128];                          // 16 bytes per lane, the first 8 used
         int32_t nm[64], ent[64], bnd[64];
@@ -971,6 +990,19 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         }
         if (lane == 0) T->ks = kacc;
     };
+    // copy of the shared fragment of the record just written to ring slot t_slot (the
+    // record is re-read from LDS: this wave wrote it, and LDS accesses of a wave are ordered)
+    auto share = [&](const KTab *T, int t_slot) {
+        if constexpr (SHARE) {
+            double *d = sh.dst + t_slot * 512;
+            const int lk = lane >> 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t o = T->kofs[4 * (2 * q + sh.kodd) + lk][sh.slot];
+                dma16((sh.ok && o >= 0) ? sh.X + o + sh.ipair : g_zero_word, d + q * 128);
+            }
+        }
+    };
     // Staging set p serves the iterations s with s % kLag == p: it holds the offsets of
     // stage s + LEAD, the entries of stage s + LEAD + kLag and the bounds of stage
     // s + LEAD + 2 kLag; registers keep np(s + LEAD) (npw), np(s + LEAD + kLag) (npo) and the
@@ -989,6 +1021,7 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
             const bool ok = tp < np_of(bt[t], t);
             const int32_t ec = ok ? et[t] : 0;
             write_tab(&ring[t], g.gl_offd[(int64_t)ec * 4 + tk], g.gl_nm[ec], ok, np_of(bt[t], t));
+            share(&ring[t], t);
         }
         __builtin_amdgcn_s_waitcnt(0);             // nothing of the prologue left in flight
 #pragma unroll
@@ -1006,12 +1039,24 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
     lds_barrier();
     int slot = LEAD;                               // ring slot of stage s + LEAD
     auto phase = [&](int s, Staging *P, int32_t &nw, int32_t &no, bool &ko, bool &ke) {
-        __builtin_amdgcn_s_waitcnt(0x0F7C);        // vmcnt(12): this set's loads have landed
+        // this set's loads have landed: vmcnt(12).  With SHARE a phase issues four copies
+        // before its four loads while the prologue issued the four sets alone, so phase
+        // q < kLag finds 12 + 4q loads issued after its set (vmcnt(12 + 4q)), every later
+        // phase 24 (vmcnt(24), which also covers the copies of phase s - kLag)
+        if constexpr (SHARE) {
+            if (s >= 3) __builtin_amdgcn_s_waitcnt(0x4F78);          // vmcnt(24)
+            else if (s == 2) __builtin_amdgcn_s_waitcnt(0x4F74);     // vmcnt(20)
+            else if (s == 1) __builtin_amdgcn_s_waitcnt(0x4F70);     // vmcnt(16)
+            else __builtin_amdgcn_s_waitcnt(0x0F7C);                 // vmcnt(12)
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0F7C);
+        }
         const int64_t o = P->off[2 * lane];
         const int32_t m = P->nm[lane];
         const int32_t er = P->ent[lane];
         const int32_t br = P->bnd[lane];
         write_tab(&ring[slot], o, m, ko, nw);      // stage s + LEAD
+        share(&ring[slot], slot);
         slot = slot == kSlots - 1 ? 0 : slot + 1;
         issue_offsets(er, ke, P);                  // stage s + LEAD + kLag
         nw = no;
@@ -1064,9 +1109,29 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     const int nst = (int)(g.stage_off[u + 1] - s0), npairs = (int)(g.pair_off[u + 1] - p0);
     const int lr = lane & 15, lk = lane >> 4;
 
+    // SHARE (several consumer waves, every cluster size even): the record wave copies the
+    // shared 16-row side into LDS five stages ahead and the consumers load only their own
+    // block from global memory
+    constexpr bool SHARE = WAVES > 2 && PAIRED;
+    constexpr int LEAD = SHARE ? 5 : 3;
+    constexpr int kSlots = LEAD + 1;
+    double *const shr = lds + ring_bytes<LEAD>() / sizeof(double);
+    const bool shA = g.RB == 1;                        // the shared side: rows (else columns)
+    const bool odd = (lr & 1) != 0;
     if (wave == producer) {
         const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
-        record_producer<3>(g, ui, lds, ring, lane);
+        SharedSide sh{};
+        if constexpr (SHARE) {
+            const int ssz = shA ? sr : sc, sng = shA ? ngr : ngc;
+            const int kx = lr / ssz, ix = lr - kx * ssz;
+            sh.X = shA ? A : B;
+            sh.dst = shr;
+            sh.slot = (shA ? 0 : 4) + (kx & 3);
+            sh.ipair = odd ? ix - 1 : ix;
+            sh.kodd = odd ? 1 : 0;
+            sh.ok = kx < sng && ix < (shA ? sel4(kx & 3, nr0, nr1, nr2, nr3) : sel4(kx & 3, nc0, nc1, nc2, nc3));
+        }
+        record_producer<LEAD, SHARE>(g, ui, lds, ring, lane, sh);
         return;
     }
     if (wave >= nblk) {                                // no block: take part in the barriers only
@@ -1091,7 +1156,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     // at k step j + 1; one value is swapped between them when the quarter is computed.
     // Without PAIRED a lane loads its own row at both steps.
     typedef double dbl2 __attribute__((ext_vector_type(2)));
-    const bool odd = (lr & 1) != 0;
     const int iap = PAIRED && odd ? ia - 1 : ia, jbp = PAIRED && odd ? jb - 1 : jb;
     auto load_q = [&](const KTab *T, int q, dbl2 &va, dbl2 &vb) {
         if constexpr (PAIRED) {
@@ -1108,6 +1172,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
                 vb[h] = *((okb && ob >= 0) ? B + ob + jb : zero);
             }
         }
+    };
+    // SHARE: the wave's own side only (the block of the wide side it computes)
+    const double *const own = shA ? B : A;
+    const bool ook = shA ? okb : oka;
+    const int oslot = shA ? slotb : slota, oip = shA ? jbp : iap;
+    auto load_own = [&](const KTab *T, int q, dbl2 &v) {
+        const int64_t o = T->kofs[4 * (2 * q + (odd ? 1 : 0)) + lk][oslot];
+        const bool live = ook && o >= 0;
+        v = *reinterpret_cast<const dbl2 *>(live ? own + o + oip : zero);
+        return live;
     };
     dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
     // rows at and past the stage's k count have no record (offset -1) and load zeros, so
@@ -1126,36 +1200,82 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
     };
-    dbl2 qa[8], qb[8];
-    lds_barrier();
-    // (issued in ring order: the loop's waits count on set 0 being the oldest)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        load_q(&ring[q >> 2], q & 3, qa[q], qb[q]);
-        __builtin_amdgcn_sched_barrier(0);
-    }
     // stage s is in sets 4 (s & 1) .. 4 (s & 1) + 3; past the last stage the records have
     // no rows, so the refills are unconditional and load zeros.  Units have an even
     // number of stages, so the loop body (two stages) has no exit in its middle, which
     // would make the compiler wait for loads at the loop head that are still in flight.
-    int slot = 2;                                      // ring slot of stage s + 2
-    for (int s = 0; s < nst; s += 2) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            comp_q(qa[q], qb[q]);
-            load_q(&ring[slot], q, qa[q], qb[q]);
-            __builtin_amdgcn_sched_barrier(0);     // a quarter's swaps must not move ahead
-        }
-        slot = (slot + 1) & 3;
+    // Loads are issued in ring order (the loop's waits count on set 0 being the oldest).
+    if constexpr (SHARE) {
+        // A stage in which no function of the wave's own block meets a middle cluster of
+        // the stage adds only zeros: its MFMAs are skipped (a wave-uniform branch; the
+        // flag is taken from the lanes' record entries when the stage's loads are issued).
+        dbl2 qo[8];
+        bool act[2];
         lds_barrier();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            comp_q(qa[4 + q], qb[4 + q]);
-            load_q(&ring[slot], q, qa[4 + q], qb[4 + q]);
+        for (int h = 0; h < 2; ++h) {
+            bool live = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                live |= load_own(&ring[h], q, qo[4 * h + q]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            act[h] = __builtin_amdgcn_ballot_w64(live) != 0;
+        }
+        int slot = 2, shs = 0;                         // ring slots of stages s + 2 and s
+        auto half = [&](int h) {
+            const int base = 4 * h;
+            const dbl2 *sp = reinterpret_cast<const dbl2 *>(shr + shs * 512) + lane;
+            dbl2 sv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sv[q] = sp[q * 64];
+            const bool run = act[h];
+            bool live = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (run) {
+                    const dbl2 va = shA ? sv[q] : qo[base + q], vb = shA ? qo[base + q] : sv[q];
+                    comp_q(va, vb);
+                }
+                live |= load_own(&ring[slot], q, qo[base + q]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            act[h] = __builtin_amdgcn_ballot_w64(live) != 0;
+            slot = slot == kSlots - 1 ? 0 : slot + 1;
+            shs = shs == kSlots - 1 ? 0 : shs + 1;
+            lds_barrier();
+        };
+        for (int s = 0; s < nst; s += 2) {
+            half(0);
+            half(1);
+        }
+    } else {
+        dbl2 qa[8], qb[8];
+        lds_barrier();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            load_q(&ring[q >> 2], q & 3, qa[q], qb[q]);
             __builtin_amdgcn_sched_barrier(0);
         }
-        slot = (slot + 1) & 3;
-        lds_barrier();
+        int slot = 2;                                  // ring slot of stage s + 2
+        for (int s = 0; s < nst; s += 2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                comp_q(qa[q], qb[q]);
+                load_q(&ring[slot], q, qa[q], qb[q]);
+                __builtin_amdgcn_sched_barrier(0);     // a quarter's swaps must not move ahead
+            }
+            slot = slot == kSlots - 1 ? 0 : slot + 1;
+            lds_barrier();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                comp_q(qa[4 + q], qb[4 + q]);
+                load_q(&ring[slot], q, qa[4 + q], qb[4 + q]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            slot = slot == kSlots - 1 ? 0 : slot + 1;
+            lds_barrier();
+        }
     }
     // store the block where it belongs to S
     const int col = 16 * cb + lr;
@@ -1244,7 +1364,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
 
     if (wave == producer) {
         const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
-        record_producer<2>(g, ui, lds, ring, lane);
+        record_producer<2, false>(g, ui, lds, ring, lane, SharedSide{});
         return;
     }
     if (wave >= nconsumer) {
@@ -1472,7 +1592,10 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
             // one side a single block: register-direct kernel, one wave per block plus the
             // record wave
             g.WR = g.WC = g.nsplit = 1;
-            const size_t ring = ring_bytes<3>();
+            // record ring and staging, then with the shared-side copies (8 waves, even
+            // sizes) their ring of six 4 KB slots
+            const bool share = wide && L.rb * L.cb > 1;
+            const size_t ring = share ? ring_bytes<5>() + 6 * 4096 : ring_bytes<3>();
             int st;
             const void *k;
             if (L.rb * L.cb == 1) k = wide ? (const void *)k_mgemm_thin<2, true> : (const void *)k_mgemm_thin<2, false>;

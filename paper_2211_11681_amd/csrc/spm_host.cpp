@@ -585,14 +585,12 @@ void build_groups(spm_pattern_s *p)
         for (auto &x : th) x.join();
     }
     // Launch classes by (row blocks, column blocks).  Inside a class the units are cut
-    // into square blocks of b x b groups (group ids follow the cluster order, so a
-    // block is a spatially compact set of row and column groups); a block's units run
-    // back to back on one XCD, so the operand panels of its few row and column groups
-    // are re-read from that XCD's L2 instead of HBM.  b is the smallest power of two
-    // whose non-empty blocks hold on average at least as many units as one XCD runs
-    // at once.  Blocks go to the XCD with the least work so far, heaviest first, and
-    // inside a block the heaviest units start first.  Workgroups are dispatched to the
-    // 8 XCDs round robin, so the launch order interleaves the eight per-XCD lists.
+    // into strips that share one operand group: the column group when the columns are
+    // the wider side, else the row group.  A strip's units run back to back on one XCD,
+    // so the shared panel is re-read from that XCD's L2 instead of HBM.  Strips go to
+    // the XCD with the least work so far, heaviest first, and inside a strip the
+    // heaviest units start first.  Workgroups are dispatched to the 8 XCDs round robin,
+    // so the launch order interleaves the eight per-XCD lists.
     auto key = [&](int64_t u) { return p->grp_R[p->unit_gr[u]] / 16 * 16 + p->grp_R[p->unit_gc[u]] / 16; };
     std::vector<int64_t> idx(nu);
     for (int64_t u = 0; u < nu; ++u) idx[u] = u;
@@ -609,32 +607,12 @@ void build_groups(spm_pattern_s *p)
             while (c1 < nu && key(idx[c1]) == key(idx[c0])) ++c1;
             const int k = key(idx[c0]);
             const int rb = k / 16, cb = k % 16;
-            // units one XCD holds at once: 32 CUs x workgroups per CU (LDS bound)
-            int per_cu = 7;
-            if (rb * cb > 1) {
-                int lxa = 4, lxb = 4;
-                while ((1 << lxa) < 16 * rb) ++lxa;
-                while ((1 << lxb) < 16 * cb) ++lxb;
-                const double lds = 2.0 * 32 * ((1 << lxa) + (1 << lxb)) * 8 + 4200;
-                per_cu = std::max(1, std::min(2, (int)(163840 / lds)));
-            }
-            const double target = 32.0 * per_cu;
-            int bsz = 1;
-            for (;; bsz *= 2) {
-                std::vector<int64_t> keys;
-                keys.reserve(c1 - c0);
-                for (int64_t i = c0; i < c1; ++i)
-                    keys.push_back((int64_t)(p->unit_gr[idx[i]] / bsz) * (1 << 20) + p->unit_gc[idx[i]] / bsz);
-                std::sort(keys.begin(), keys.end());
-                const int64_t nb = std::unique(keys.begin(), keys.end()) - keys.begin();
-                if ((double)(c1 - c0) / nb >= target || bsz >= (1 << 19)) break;
-            }
-            // blocks of the class
-            std::vector<std::pair<int64_t, int64_t>> bu;   // (block key, unit)
+            // strips of the class
+            std::vector<std::pair<int64_t, int64_t>> bu;   // (strip key, unit)
             bu.reserve(c1 - c0);
             for (int64_t i = c0; i < c1; ++i) {
                 const int64_t u = idx[i];
-                bu.push_back({(int64_t)(p->unit_gr[u] / bsz) * (1 << 20) + p->unit_gc[u] / bsz, u});
+                bu.push_back({cb > rb ? p->unit_gc[u] : p->unit_gr[u], u});
             }
             std::sort(bu.begin(), bu.end(), [&](const std::pair<int64_t, int64_t> &x, const std::pair<int64_t, int64_t> &y) {
                 if (x.first != y.first) return x.first < y.first;
