@@ -472,7 +472,9 @@ constexpr int kSP = 8;    // middle clusters per stage
 struct KTab {
     int64_t kofs[kKS][8];
     int32_t ks;           // padded k rows of the stage
-    int32_t pad[3];
+    int32_t act;          // bit q (row member q), 4 + q (column member q): the member has a
+                          // tile in some middle cluster of the stage (grouped kernel only)
+    int32_t pad[2];
 };
 
 template <int WAVES>
@@ -675,13 +677,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
             if (q == mm) { nmm = nmv[q]; kbm = kbv[q]; }
         const int kkm = kk - kbm;
         const bool live = m >= 0 && kkm < nmm;
+        int act = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t o = __shfl(t_off, mm * 8 + (rows ? 0 : 4) + q);
             const int n = nslot[q];
-            T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * n : -1;
+            const bool on = live && o >= 0;
+            T->kofs[kk][(rows ? 0 : 4) + q] = on ? o + (int64_t)kkm * n : -1;
+            const uint64_t b = __builtin_amdgcn_ballot_w64(on);
+            act |= ((uint32_t)b != 0 ? 1 << q : 0) | ((b >> 32) != 0 ? 16 << q : 0);
         }
-        if (lane == 0) T->ks = kacc;
+        if (lane == 0) {
+            T->ks = kacc;
+            T->act = act;
+        }
     };
 
     dbl4 acc[MR][MC];
@@ -695,6 +704,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     for (int i = 0; i < MR; ++i) arow[i] = 16 * min(wr + i * g.WR, g.RB - 1) + lr;
 #pragma unroll
     for (int j = 0; j < MC; ++j) bcol[j] = 16 * min(wc + j * g.WC, g.CB - 1) + lr;
+    // members covering each owned block (bits of KTab::act): a block none of whose row (or
+    // column) members has a tile in the stage's middle clusters adds only zeros
+    int amask[MR], bmask[MC];
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        const int r0 = 16 * min(wr + i * g.WR, g.RB - 1), m0 = r0 / sr, m1 = min((r0 + 15) / sr, 3);
+        amask[i] = ((2 << m1) - 1) & ~((1 << m0) - 1);
+    }
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+        const int c0 = 16 * min(wc + j * g.WC, g.CB - 1), m0 = c0 / sc, m1 = min((c0 + 15) / sc, 3);
+        bmask[j] = (((2 << m1) - 1) & ~((1 << m0) - 1)) << 4;
+    }
 
     // prologue: records of stages 0 and 1 written; in registers: offsets of stage 2,
     // entries of stage 3, bounds of stage 4 (all loads complete at the first sync)
@@ -718,7 +740,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     load_entry(fb_of(fbe), np3, e);                // stage 3
     load_bounds(4, fbe);                           // stage 4
     unit_sync<WAVES>();
-    int ks_next = ktab[0].ks;
+    int ks_next = ktab[0].ks, act_next = ktab[0].act;
     if (nst > 0) {
         gather_panel<WAVES, WIDTH>(&ktab[0], 0, A, lds, ks_next, g.lxa, wave, dl, half, gla, zero);
         gather_panel<WAVES, WIDTH>(&ktab[0], 4, B, lds + kKS * Xa, ks_next, g.lxb, wave, dl, half, glb, zero);
@@ -729,7 +751,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
     // iteration is consumed before the sync that opens the next one.
     for (int s = 0; s < nst; ++s) {
         unit_sync<WAVES>();                         // gathers of stage s landed; MFMAs of s-1 done
-        const int ks_s = ks_next;
+        const int ks_s = ks_next, act_s = act_next;
         const int np4 = np_of(fbe);
         const int32_t fb4 = fb_of(fbe);
         write_tab(&ktab[s & 1], off, nm, np2);      // stage s+2
@@ -742,6 +764,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
             const KTab *T1 = &ktab[(s + 1) & 1];
             double *buf = lds + ((s + 1) & 1) * pd;
             ks_next = T1->ks;
+            act_next = T1->act;
             gather_panel<WAVES, WIDTH>(T1, 0, A, buf, ks_next, g.lxa, wave, dl, half, gla, zero);
             gather_panel<WAVES, WIDTH>(T1, 4, B, buf + kKS * Xa, ks_next, g.lxb, wave, dl, half, glb, zero);
         }
@@ -761,6 +784,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
 #pragma unroll
                     for (int j = 0; j < MC; ++j) fb[t][j] = sB[kr * Xb + bcol[j]];
                 }
+                bool on[MR][MC];
+#pragma unroll
+                for (int i = 0; i < MR; ++i)
+#pragma unroll
+                    for (int j = 0; j < MC; ++j) on[i][j] = (act_s & amask[i]) != 0 && (act_s & bmask[j]) != 0;
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
                     if (4 * (kslice + t * nsplit) < ks_s)
@@ -768,7 +796,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
                         for (int i = 0; i < MR; ++i)
 #pragma unroll
                             for (int j = 0; j < MC; ++j)
-                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[t][i], fb[t][j], acc[i][j], 0, 0, 0);
+                                if (on[i][j])
+                                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[t][i], fb[t][j], acc[i][j], 0, 0, 0);
             } else {
                 // fragments of the next k step are read while the MFMAs of this one run
                 int k0 = 4 * kslice;
