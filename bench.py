@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
+    ap.add_argument("--workload", default="product", choices=["product", "newton_schulz", "gp_gradient"],
+                    help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
+                         "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
+                         "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072)")
     return ap.parse_args()
 
 
@@ -130,6 +134,109 @@ def recorded_traffic():
     return float(fields["hbm_bytes_per_product"])
 
 
+NS_WORKLOAD = dict(workload="newton_schulz_cube3", n=262144, dim=3, kernel="matern_nu2.5", lengthscale=0.2,
+                   vanishing_moments_degree=1, leaf=32, eta=1.0, seed=4, mu=1e-2, iterations=20, final_f64=3)
+GP_WORKLOAD = dict(workload="gp_lengthscale_gradient_sphere", n=131072, kernel="matern_nu1.5", lengthscale=0.3,
+                   vanishing_moments_degree=1, leaf=32, eta=1.0, seed=5, mu=1e-2, iterations=15, fd_step=1e-4)
+
+
+def _timed(fn):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1)
+
+
+def newton_schulz_main(args):
+    """Masked Newton-Schulz inverse of A = K + mu I: N = 262144 points in the unit cube
+    (seed 4), Matern nu = 5/2, l = 0.2, scaled by 1/N, degree 1, leaf 32, eta = 1.0.
+    20 iterations (40 products and the residual product), once all in FP64 and once
+    with the bulk in F32ACC and the last 3 iterations in FP64."""
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    w = dict(NS_WORKLOAD)
+    n = args.n if args.n != WORKLOAD["n"] else w["n"]
+    w["n"] = n
+    print(f"[bench] newton_schulz: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
+    pts = synth.points_cube(n, w["dim"], w["seed"])
+    t0 = time.perf_counter()
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    A = S.kernel_compress(pat, tree, 2, w["lengthscale"], 1.0 / n)
+    S.axpy(pat, w["mu"], None, 1.0, A)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    alpha0 = 2.0 / (1.0 + 2.0 * w["mu"])
+    runs = {}
+    for bulk in ("f64", "f32acc"):
+        S.newton_schulz(pat, A, 1, 1, bulk, alpha0)                    # warm-up (scratch, kernels)
+        (X, res, _), ms = _timed(lambda: S.newton_schulz(pat, A, w["iterations"], w["final_f64"], bulk, alpha0))
+        r = res.cpu().tolist()
+        runs[bulk] = {"ms": ms, "ms_per_product": ms / (2 * w["iterations"] + 1), "residual_final": r[-1],
+                      "residuals": r}
+        print(f"[bench] NS bulk {bulk}: {ms:.1f} ms, final residual {r[-1]:.3e}", file=sys.stderr, flush=True)
+        del X
+    out = {"metric": "masked Newton-Schulz inverse, 20 iterations (41 products), final residual ||I - P_S(A X)||_F/sqrt(N)",
+           "value": 1e3 / runs["f64"]["ms"], "unit": "inverses/s (all FP64)", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs, setup_s=t_setup),
+           "runs": runs, "speedup_f32acc_bulk_vs_f64": runs["f64"]["ms"] / runs["f32acc"]["ms"]}
+    print(json.dumps(out), flush=True)
+
+
+def gp_gradient_main(args):
+    """f(l) = y^T X_15(K^eta(l) + mu I) y and df/dl by reverse mode through the 15
+    Newton-Schulz iterations (per-iteration checkpoints), checked against a central
+    difference of two further forward passes.  Points on the unit sphere (seed 5),
+    Matern nu = 3/2, l = 0.3, scaled by 1/N, y ~ N(0, I) in samplet coordinates."""
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import autograd as AG
+    from paper_2211_11681_amd import spm as S
+
+    w = dict(GP_WORKLOAD)
+    n = args.n if args.n != WORKLOAD["n"] else w["n"]
+    w["n"] = n
+    print(f"[bench] gp_gradient: building tree and pattern for n={n}", file=sys.stderr, flush=True)
+    pts = synth.points_sphere(n, w["seed"])
+    t0 = time.perf_counter()
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    y = torch.from_numpy(synth.normals(n, 100 + w["seed"])).cuda()
+    alpha0 = 2.0 / (1.0 + 2.0 * w["mu"])
+    iters, ell, mu = w["iterations"], w["lengthscale"], w["mu"]
+    (f, g, res), ms = _timed(lambda: AG.gp_quadform_and_grad(pat, tree, 1, ell, mu, y, iters, alpha0, 1.0 / n))
+
+    def forward(l):
+        K = S.kernel_compress(pat, tree, 1, l, 1.0 / n)
+        S.axpy(pat, mu, None, 1.0, K)
+        X, _, _ = S.newton_schulz(pat, K, iters, iters, "f64", alpha0)
+        return float(S.quadform(pat, X, y))
+
+    h = w["fd_step"]
+    (fp, fm), ms_fd = _timed(lambda: (forward(ell + h), forward(ell - h)))
+    g_fd = (fp - fm) / (2 * h)
+    print(f"[bench] GP: f {f:.12e} df/dl {g:.12e} FD {g_fd:.12e}, {ms:.1f} ms", file=sys.stderr, flush=True)
+    out = {"metric": "GP objective and lengthscale gradient through 15 Newton-Schulz iterations (reverse mode)",
+           "value": 1e3 / ms, "unit": "gradients/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs, setup_s=t_setup),
+           "ms_forward_and_backward": ms, "products": 2 * iters + 5 * iters,
+           "f": f, "df_dl": g, "df_dl_central_difference": g_fd, "rel_diff_vs_fd": abs(g - g_fd) / abs(g),
+           "residual_final": float(res[-1]), "ms_two_forward_passes_for_fd": ms_fd}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +253,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "newton_schulz":
+        return newton_schulz_main(args)
+    if args.workload == "gp_gradient":
+        return gp_gradient_main(args)
     n = args.n
     w = WORKLOAD
     print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
