@@ -1019,6 +1019,39 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         }
         if (lane == 0) T->ks = kacc;
     };
+    // The same record built from the staging set of the loop: the stage's cluster sizes go
+    // to scalar registers, whose bit masks of cluster starts (B) and of live rows (L) give
+    // each lane kk its cluster (the set bits of B up to kk) and whether row kk exists; the
+    // tile offsets are read from the staged copy of the union entries.
+    auto write_tab_stg = [&](KTab *T, const Staging *P, int32_t m_raw, bool ok, int t_np) {
+        const int t_nm = (ok && tslot == 0) ? m_raw : 0;
+        uint64_t Bm = 0, Lm = 0;
+        int kb = 0;
+#pragma unroll
+        for (int q = 0; q < kSP; ++q) {
+            const int nmq = __builtin_amdgcn_readlane(t_nm, q * 8);
+            if (q < t_np) {
+                Bm |= 1ull << kb;
+                Lm |= ((1ull << nmq) - 1) << kb;
+                kb += (nmq + 3) & ~3;
+            }
+        }
+        const int kk = lane & 31;
+        const bool rows = lane < 32;
+        const uint32_t Bw = (uint32_t)Bm, Lw = (uint32_t)Lm;
+        const bool live = ((Lw >> kk) & 1u) != 0;
+        const uint32_t prefix = Bw & ((2u << kk) - 1u);
+        const int m = __builtin_popcount(prefix) - 1;
+        const int kkm = kk - (prefix ? 31 - __builtin_clz(prefix) : 0);
+        const int mm = m < 0 ? 0 : m;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int sl = (rows ? 0 : 4) + q;
+            const int64_t o = P->off[2 * (mm * 8 + sl)];
+            T->kofs[kk][sl] = (live && o >= 0) ? o + (int64_t)kkm * nslot[q] : -1;
+        }
+        if (lane == 0) T->ks = kb;
+    };
     // copy of the shared fragment of the record just written to ring slot t_slot (the
     // record is re-read from LDS: this wave wrote it, and LDS accesses of a wave are ordered)
     auto share = [&](const KTab *T, int t_slot) {
@@ -1080,11 +1113,10 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         } else {
             __builtin_amdgcn_s_waitcnt(0x0F7C);
         }
-        const int64_t o = P->off[2 * lane];
         const int32_t m = P->nm[lane];
         const int32_t er = P->ent[lane];
         const int32_t br = P->bnd[lane];
-        write_tab(&ring[slot], o, m, ko, nw);      // stage s + LEAD
+        write_tab_stg(&ring[slot], P, m, ko, nw);  // stage s + LEAD
         share(&ring[slot], slot);
         slot = slot == kSlots - 1 ? 0 : slot + 1;
         issue_offsets(er, ke, P);                  // stage s + LEAD + kLag
