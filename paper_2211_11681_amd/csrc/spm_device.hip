@@ -1244,22 +1244,27 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
         v = *reinterpret_cast<const dbl2 *>(live ? own + o + oip : zero);
         return live;
     };
-    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    // two accumulators (even and odd k steps), so that consecutive MFMAs of a wave do not
+    // wait for each other; they are added once at the end
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0}, acc1 = dbl4{0.0, 0.0, 0.0, 0.0};
     // rows at and past the stage's k count have no record (offset -1) and load zeros, so
     // every k step runs unconditionally: straight-line code lets each MFMA wait for its
     // own loads only
+    // even lane: (x, partner's x), odd lane: (partner's y, y); each moved value has one
+    // use, so the compiler folds the lane move into the select
+    auto unpair = [&](const dbl2 &v, double &f0, double &f1) {
+        const double px = swap_adjacent(v.x), py = swap_adjacent(v.y);
+        f0 = odd ? py : v.x;
+        f1 = odd ? v.y : px;
+    };
     auto comp_q = [&](const dbl2 &va, const dbl2 &vb) {
         double a0 = va.x, a1 = va.y, b0 = vb.x, b1 = vb.y;
         if constexpr (PAIRED) {
-            const double xa = swap_adjacent(odd ? va.x : va.y);
-            const double xb = swap_adjacent(odd ? vb.x : vb.y);
-            a0 = odd ? xa : va.x;
-            a1 = odd ? va.y : xa;
-            b0 = odd ? xb : vb.x;
-            b1 = odd ? vb.y : xb;
+            unpair(va, a0, a1);
+            unpair(vb, b0, b1);
         }
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
     };
     // stage s is in sets 4 (s & 1) .. 4 (s & 1) + 3; past the last stage the records have
     // no rows, so the refills are unconditional and load zeros.  Units have an even
@@ -1338,6 +1343,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
             lds_barrier();
         }
     }
+    acc += acc1;
     // store the block where it belongs to S
     const int col = 16 * cb + lr;
     const int kc = col / sc, jj = col - kc * sc;
