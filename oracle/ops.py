@@ -15,6 +15,14 @@
 * ``ns_backward``: reverse mode of the iteration for f = y^T X_K y.
 * ``error_estimator``: e_F(A) = ||A X||_F / ||X||_F with X in U[0,1]^{N x 10}
   (Section 5.1).
+* ``expm_taylor``: the power series of the exponential (end of Section 4) cut
+  after ``terms`` terms and evaluated in the S-format by Horner's rule, every
+  product formatted: E = I, then E <- I + P_S(A E) / k for k = terms .. 1.  The
+  paper does not fix the evaluation order of the series; Horner's rule is the
+  reading taken here.
+* ``expm_series_apply``: exp(A) X by the series applied to a block X without
+  any pattern (the paper's reference for its exponential errors, Section 5,
+  30 terms).
 """
 from __future__ import annotations
 
@@ -107,3 +115,23 @@ def column_local_inverse(a: np.ndarray, mask: np.ndarray) -> np.ndarray:
 
 def error_estimator(a: np.ndarray, xprobe: np.ndarray) -> float:
     return float(np.linalg.norm(a @ xprobe) / np.linalg.norm(xprobe))
+
+
+def expm_taylor(a: np.ndarray, mask: np.ndarray, terms: int) -> np.ndarray:
+    """sum_{j <= terms} A^j / j! in the S-format (Horner, formatted products)."""
+    n = a.shape[0]
+    eye = np.eye(n)
+    e = np.where(mask, eye, 0.0)
+    for k in range(terms, 0, -1):
+        e = np.where(mask, eye + masked_product(a, e, mask) / k, 0.0)
+    return e
+
+
+def expm_series_apply(a: np.ndarray, x: np.ndarray, terms: int = 30) -> np.ndarray:
+    """sum_{j <= terms} A^j X / j!, the powers applied to X one at a time."""
+    out = x.copy()
+    t = x.copy()
+    for j in range(1, terms + 1):
+        t = a @ t / j
+        out = out + t
+    return out

@@ -178,3 +178,61 @@ def test_sampled_rows_product_matches_full(cfg1_setup):
     assert cnt == sum(rp[r + 1] - rp[r] for r in rows)
     for r in rows:
         assert np.array_equal(part[rp[r]:rp[r + 1]], full[rp[r]:rp[r + 1]])
+
+
+def test_expm_taylor_full_pattern_is_library_expm():
+    # With S = everything the formatted series is the plain truncated Taylor series of
+    # exp(A); 20 terms at ||A||_2 <= 0.6 leave a remainder below 1e-20.
+    import scipy.linalg
+    rng = np.random.default_rng(3)
+    n = 40
+    a = rng.standard_normal((n, n))
+    a *= 0.6 / np.linalg.norm(a, 2)
+    full = np.ones((n, n), bool)
+    e = ops.expm_taylor(a, full, 20)
+    ref = scipy.linalg.expm(a)
+    assert np.linalg.norm(e - ref) <= 1e-13 * np.linalg.norm(ref)
+    # the series applied to a block agrees with the same library routine
+    x = rng.uniform(size=(n, 10))
+    assert np.linalg.norm(ops.expm_series_apply(a, x, 30) - ref @ x) <= 1e-13 * np.linalg.norm(ref @ x)
+    # the error estimator of a scaled identity is the scale
+    assert abs(ops.error_estimator(-2.5 * np.eye(n), x) - 2.5) < 1e-14
+
+
+def test_expm_taylor_diagonal_and_block_patterns():
+    import math
+
+    import scipy.linalg
+    rng = np.random.default_rng(4)
+    n = 24
+    # diagonal pattern: each entry is the scalar series of its own exponential
+    d = rng.uniform(-0.5, 0.5, n)
+    e = ops.expm_taylor(np.diag(d), np.eye(n, dtype=bool), 12)
+    ref = np.array([sum(v ** j / math.factorial(j) for j in range(13)) for v in d])
+    assert np.allclose(np.diag(e), ref, rtol=0, atol=1e-15) and np.count_nonzero(e - np.diag(np.diag(e))) == 0
+    # block-diagonal pattern: blocks do not interact, each is its own exponential
+    mask = np.zeros((n, n), bool)
+    for b0, b1 in [(0, 5), (5, 14), (14, 24)]:
+        mask[b0:b1, b0:b1] = True
+    a = np.where(mask, rng.standard_normal((n, n)) * 0.1, 0.0)
+    e = ops.expm_taylor(a, mask, 20)
+    for b0, b1 in [(0, 5), (5, 14), (14, 24)]:
+        blk = scipy.linalg.expm(a[b0:b1, b0:b1])
+        assert np.linalg.norm(e[b0:b1, b0:b1] - blk) <= 1e-14 * np.linalg.norm(blk)
+    assert np.count_nonzero(e[~mask]) == 0
+
+
+def test_expm_taylor_error_on_compressed_kernel(cfg1_setup):
+    # The paper's measure (Section 5): e_F(exp(K) X - E X) with exp(K) X from 30 terms
+    # of the series applied to X.  K^eta (scaled by 1/N, so ||K||_2 <= 1) is
+    # compressible: the truncation error falls with the terms until the compression
+    # error is reached.
+    pr = cfg1_setup
+    mask = pr["mask_prior"]
+    a = np.where(mask, pr["ks"], 0.0)
+    x = np.random.default_rng(5).uniform(size=(a.shape[0], 10))
+    ref = ops.expm_series_apply(a, x, 30)
+    err = {t: np.linalg.norm(ref - ops.expm_taylor(a, mask, t) @ x) / np.linalg.norm(x) for t in (1, 3, 12)}
+    print("e_F by terms:", {t: f"{v:.2e}" for t, v in err.items()})
+    assert err[12] < err[3] < err[1]
+    assert err[12] < 1e-6
