@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
-    ap.add_argument("--workload", default="product", choices=["product", "newton_schulz", "gp_gradient"],
+    ap.add_argument("--workload", default="product", choices=["product", "newton_schulz", "gp_gradient", "expm"],
                     help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
                          "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
-                         "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072)")
+                         "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072); "
+                         "expm: the truncated exponential series of K (10 terms) on the product workload")
     return ap.parse_args()
 
 
@@ -237,6 +238,35 @@ def gp_gradient_main(args):
     print(json.dumps(out), flush=True)
 
 
+def expm_main(args):
+    """exp(K) by its power series cut after 10 terms, Horner's rule with formatted
+    products, on the product benchmark's K (N = 131072 cube, exponential kernel)."""
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    w = dict(WORKLOAD, workload="expm_taylor_cube3", terms=10)
+    n = args.n
+    w["n"] = n
+    print(f"[bench] expm: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
+    pts = synth.points_cube(n, w["dim"], w["seed"])
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    K = S.kernel_compress(pat, tree, 0, w["lengthscale"], 1.0 / n)
+    E = pat.empty("f64")
+    S.expm_taylor(pat, K, 1, out=E)                                     # warm-up
+    reps = max(1, args.steps // 2)
+    _, ms = _timed(lambda: [S.expm_taylor(pat, K, w["terms"], out=E) for _ in range(reps)])
+    ms /= reps
+    print(f"[bench] expm: {ms:.1f} ms for {w['terms']} terms", file=sys.stderr, flush=True)
+    out = {"metric": "truncated exponential series exp(K) on S, 10 terms (10 masked products)",
+           "value": 1e3 / ms, "unit": "exponentials/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic", "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
+           "ms": ms, "ms_per_product": ms / w["terms"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -257,6 +287,8 @@ def main():
         return newton_schulz_main(args)
     if args.workload == "gp_gradient":
         return gp_gradient_main(args)
+    if args.workload == "expm":
+        return expm_main(args)
     n = args.n
     w = WORKLOAD
     print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)

@@ -186,6 +186,19 @@ int spm_quadform(spm_pattern p, const double *X, const double *y, double *out, v
 /* X = alpha P_S(y y^T) (the seed of the quadratic-form adjoint). */
 int spm_fill_outer(spm_pattern p, double alpha, const double *y, double *X, void *stream);
 
+/* Truncated power series of exp(A) on S (the exponential's series at the end of
+ * Section 4; its errors are reported in Section 5), FP64, by Horner's rule with
+ * formatted products:
+ *   E = I;  for k = terms, ..., 1:  E <- I + P_S(A E) / k,
+ * so that on the full pattern E = sum_{j <= terms} A^j / j!.  A and E are device
+ * F64 value arrays (distinct); terms >= 0 (0 gives E = I).  scratch: device
+ * workspace of at least spm_expm_taylor_scratch() bytes (one value array), unused
+ * when terms = 0.  Asynchronous on the stream; EINVAL on null or overlapping
+ * buffers, a negative term count or a short scratch. */
+int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes);
+int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, void *scratch,
+                    size_t scratch_bytes, void *stream);
+
 /* Masked Newton-Schulz inverse of A (FP64 on S):
  *   X_0 = alpha0 I;  for k = 0..iters-1:  Y_k = P_S(A X_k),  r_k = ||I - Y_k||_F / sqrt(n),
  *   Z_k = 2I - Y_k,  X_{k+1} = P_S(X_k Z_k);  finally r_iters = ||I - P_S(A X_iters)||_F / sqrt(n).

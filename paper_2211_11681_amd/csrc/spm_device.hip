@@ -2019,6 +2019,41 @@ size_t ns_scratch(spm_pattern p, int bulk, int32_t nbulk)
 
 }  // namespace
 
+extern "C" int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPM_EINVAL, "spm_expm_taylor_scratch: null pointer");
+    *bytes = (size_t)p->n_stored * sizeof(double);
+    return SPM_OK;
+}
+
+// Power series of exp(A) (end of Section 4) cut after `terms` terms, Horner's rule with
+// formatted products: E = I; E <- I + P_S(A E) / k for k = terms .. 1.  The two value
+// arrays E and scratch alternate; each step is one masked product and one pass that
+// scales by 1/k and adds the identity.
+extern "C" int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, void *scratch,
+                               size_t scratch_bytes, void *stream)
+{
+    if (!p || !A || !E) return fail(SPM_EINVAL, "spm_expm_taylor: null pointer");
+    if (terms < 0) return fail(SPM_EINVAL, "spm_expm_taylor: negative number of terms");
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double);
+    if (terms > 0 && (!scratch || scratch_bytes < vb8)) return fail(SPM_EINVAL, "spm_expm_taylor: scratch too small");
+    if (overlap(A, E, vb8) || (terms > 0 && (overlap2(A, vb8, scratch, vb8) || overlap2(E, vb8, scratch, vb8))))
+        return fail(SPM_EINVAL, "spm_expm_taylor: buffers overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ns = p->n_stored;
+    double *cur = E, *oth = static_cast<double *>(scratch);
+    int st;
+    hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)cur);
+    if ((st = spm::launch_axpy(p, SPM_F64, 1.0, nullptr, 1.0, cur, s))) return st;
+    for (int32_t k = terms; k >= 1; --k) {
+        if ((st = spm::launch_gemm(p, SPM_F64, A, 0, cur, 0, oth, s))) return st;
+        if ((st = spm::launch_axpy(p, SPM_F64, 1.0, nullptr, 1.0 / k, oth, s))) return st;   // oth/k + I
+        std::swap(cur, oth);
+    }
+    if (cur != E) SPM_HIP(hipMemcpyAsync(E, cur, vb8, hipMemcpyDeviceToDevice, s));
+    return SPM_OK;
+}
+
 extern "C" int spm_newton_schulz_scratch(spm_pattern p, int bulk, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPM_EINVAL, "spm_newton_schulz_scratch: null pointer");

@@ -217,6 +217,16 @@ def fill_outer(pat: Pattern, y, alpha=1.0, out=None) -> torch.Tensor:
     return out
 
 
+def expm_taylor(pat: Pattern, A: torch.Tensor, terms: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """sum_{j <= terms} A^j / j! on S by Horner's rule with formatted products (FP64)."""
+    need = ctypes.c_size_t()
+    call("spm_expm_taylor_scratch", pat._h, ctypes.byref(need))
+    scratch = torch.empty((need.value + 7) // 8, dtype=torch.float64, device=A.device)
+    E = pat.empty("f64") if out is None else out
+    call("spm_expm_taylor", pat._h, _ptr(A), _ptr(E), int(terms), _ptr(scratch), scratch.numel() * 8, _stream())
+    return E
+
+
 def newton_schulz(pat: Pattern, A: torch.Tensor, iters: int, n_final_f64: int = 3, bulk="f64",
                   alpha0: float = 1.0, checkpoints: bool = False):
     """Masked Newton-Schulz; returns (X, residuals[iters+1], list of X_0..X_iters or None)."""

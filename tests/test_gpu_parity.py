@@ -276,3 +276,24 @@ def test_newton_schulz_vs_oracle(S):
         rb = resb.cpu().numpy()
         print(f"NS bulk={bulk}: final residual {rb[-1]:.3e} (fp64 {res[-1]:.3e})")
         assert rb[-1] < 1e-8
+
+
+@pytest.mark.parametrize("kind,n,leaf,q,eta,seed,p,ell", [("cube3", 4096, 32, 1, 1.0, 2, 0, 0.3),
+                                                          ("cube2", 2048, 16, 1, 1.6, 1, 1, 0.5)])
+def test_expm_taylor_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell):
+    # truncated exponential series on S (Horner, formatted products), 10 terms, on the
+    # oracle's K^eta uploaded to the tile layout
+    print(f"case: expm_taylor {kind} n={n} leaf={leaf} q={q} eta={eta} matern p={p} l={ell}", flush=True)
+    pr = oracle_problem(kind, n, leaf, q, eta, seed, p, ell)
+    pat = S.Pattern.from_csr(n, pr["rp"], pr["col"], pr["basis"].cluster_start)
+    mask = pr["mask"]
+    a = np.where(mask, pr["ks"], 0.0)
+    K = pat.values_from_csr(to_dev(a[mask]))
+    E = S.expm_taylor(pat, K, 10)
+    ref = ops.expm_taylor(a, mask, 10)[mask]
+    err = relerr(pat.values_to_csr(E).cpu().numpy(), ref)
+    print(f"expm_taylor: relative Frobenius error vs oracle {err:.3e}")
+    assert err < TOL64
+    # no terms: the identity, exactly
+    E0 = S.expm_taylor(pat, K, 0)
+    assert np.array_equal(pat.values_to_csr(E0).cpu().numpy(), np.eye(n)[mask])
