@@ -187,7 +187,7 @@ int spm_quadform(spm_pattern p, const double *X, const double *y, double *out, v
 int spm_fill_outer(spm_pattern p, double alpha, const double *y, double *X, void *stream);
 
 /* Truncated power series of exp(A) on S (the exponential's series at the end of
- * Section 4; its errors are reported in Section 5), FP64, by Horner's rule with
+ * Section 4.4; its errors are reported in Section 5.3), FP64, by Horner's rule with
  * formatted products:
  *   E = I;  for k = terms, ..., 1:  E <- I + P_S(A E) / k,
  * so that on the full pattern E = sum_{j <= terms} A^j / j!.  A and E are device

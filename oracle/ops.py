@@ -15,14 +15,21 @@
 * ``ns_backward``: reverse mode of the iteration for f = y^T X_K y.
 * ``error_estimator``: e_F(A) = ||A X||_F / ||X||_F with X in U[0,1]^{N x 10}
   (Section 5.1).
-* ``expm_taylor``: the power series of the exponential (end of Section 4) cut
+* ``expm_taylor``: the power series of the exponential (end of Section 4.4) cut
   after ``terms`` terms and evaluated in the S-format by Horner's rule, every
   product formatted: E = I, then E <- I + P_S(A E) / k for k = terms .. 1.  The
   paper does not fix the evaluation order of the series; Horner's rule is the
   reading taken here.
 * ``expm_series_apply``: exp(A) X by the series applied to a block X without
-  any pattern (the paper's reference for its exponential errors, Section 5,
+  any pattern (the paper's reference for its exponential errors, Section 5.3,
   30 terms).
+* ``ns_sqrt``: coupled Newton-Schulz iteration for A^{1/2} and A^{-1/2} with
+  every product formatted: Y_0 = A, Z_0 = I, T_k = (3I - P_S(Z_k Y_k)) / 2,
+  Y_{k+1} = P_S(Y_k T_k), Z_{k+1} = P_S(T_k Z_k).  The paper computes the
+  square root of a kernel matrix on the pattern by a contour integral, with its
+  inverse square root lemma for compressibility (Section 4.4), and measures it
+  by e_F(A^{1/2} A^{1/2} - A) (Section 5.3); this iteration, which converges for
+  ||I - A|| < 1, stands in for the contour integral.
 """
 from __future__ import annotations
 
@@ -135,3 +142,18 @@ def expm_series_apply(a: np.ndarray, x: np.ndarray, terms: int = 30) -> np.ndarr
         t = a @ t / j
         out = out + t
     return out
+
+
+def ns_sqrt(a: np.ndarray, mask: np.ndarray, iters: int):
+    """Returns (Y, Z, residuals ||I - P_S(Z_k Y_k)||_F / sqrt(N) for k = 0..iters-1)."""
+    n = a.shape[0]
+    eye = np.eye(n)
+    y = np.where(mask, a, 0.0)
+    z = np.where(mask, eye, 0.0)
+    res = []
+    for _ in range(iters):
+        w = masked_product(z, y, mask)
+        res.append(float(np.linalg.norm(eye - w) / np.sqrt(n)))
+        t = np.where(mask, 0.5 * (3.0 * eye - w), 0.0)
+        y, z = masked_product(y, t, mask), masked_product(t, z, mask)
+    return y, z, res

@@ -2026,7 +2026,7 @@ extern "C" int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes)
     return SPM_OK;
 }
 
-// Power series of exp(A) (end of Section 4) cut after `terms` terms, Horner's rule with
+// Power series of exp(A) (end of Section 4.4) cut after `terms` terms, Horner's rule with
 // formatted products: E = I; E <- I + P_S(A E) / k for k = terms .. 1.  The two value
 // arrays E and scratch alternate; each step is one masked product and one pass that
 // scales by 1/k and adds the identity.

@@ -236,3 +236,57 @@ def test_expm_taylor_error_on_compressed_kernel(cfg1_setup):
     print("e_F by terms:", {t: f"{v:.2e}" for t, v in err.items()})
     assert err[12] < err[3] < err[1]
     assert err[12] < 1e-6
+
+
+def test_ns_sqrt_full_pattern_is_library_sqrtm():
+    # S = everything: the coupled iteration converges to the principal square root and
+    # its inverse (spectrum of A in (0, 2)); 30 iterations reach rounding level.
+    import scipy.linalg
+    rng = np.random.default_rng(6)
+    n = 30
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(0.05, 1.5, n)
+    a = (q * lam) @ q.T
+    y, z, res = ops.ns_sqrt(a, np.ones((n, n), bool), 30)
+    r = scipy.linalg.sqrtm(a).real
+    assert np.linalg.norm(y - r) <= 1e-12 * np.linalg.norm(r)
+    assert np.linalg.norm(z - np.linalg.inv(r)) <= 1e-12 * np.linalg.norm(np.linalg.inv(r))
+    assert res[-1] < 1e-13 and res[0] > res[5] > res[10]
+
+
+def test_ns_sqrt_diagonal_and_block_patterns():
+    import scipy.linalg
+    rng = np.random.default_rng(7)
+    n = 20
+    d = rng.uniform(0.1, 1.8, n)
+    y, z, _ = ops.ns_sqrt(np.diag(d), np.eye(n, dtype=bool), 40)
+    assert np.allclose(np.diag(y), np.sqrt(d), rtol=1e-14, atol=0)
+    assert np.allclose(np.diag(z), 1.0 / np.sqrt(d), rtol=1e-14, atol=0)
+    mask = np.zeros((n, n), bool)
+    blocks = [(0, 7), (7, 12), (12, 20)]
+    a = np.zeros((n, n))
+    for b0, b1 in blocks:
+        mask[b0:b1, b0:b1] = True
+        g = rng.standard_normal((b1 - b0, b1 - b0))
+        a[b0:b1, b0:b1] = np.eye(b1 - b0) + 0.3 * (g + g.T) / np.sqrt(b1 - b0)
+    assert np.linalg.norm(np.eye(n) - a, 2) < 1
+    y, z, _ = ops.ns_sqrt(a, mask, 40)
+    for b0, b1 in blocks:
+        r = scipy.linalg.sqrtm(a[b0:b1, b0:b1]).real
+        assert np.linalg.norm(y[b0:b1, b0:b1] - r) <= 1e-12 * np.linalg.norm(r)
+    assert np.count_nonzero(y[~mask]) == 0 and np.count_nonzero(z[~mask]) == 0
+
+
+def test_ns_sqrt_on_compressed_kernel(cfg1_setup):
+    # A = K^eta + 1e-2 I (K scaled by 1/N): the masked iteration settles, and the
+    # paper's measure e_F(Y Y - A) is small (the square root is compressible on S).
+    pr = cfg1_setup
+    mask = pr["mask_prior"]
+    n = pr["n"]
+    a = np.where(mask, pr["ks"], 0.0) + 1e-2 * np.eye(n)
+    y, z, res = ops.ns_sqrt(a, mask, 16)
+    x = np.random.default_rng(8).uniform(size=(n, 10))
+    e_sq = ops.error_estimator(y @ y - a, x)
+    print(f"residuals {res[0]:.2e} -> {res[-1]:.2e}; e_F(YY - A) = {e_sq:.2e}")
+    assert res[-1] < 1e-3 * res[0]
+    assert e_sq < 1e-4
