@@ -50,11 +50,13 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
-    ap.add_argument("--workload", default="product", choices=["product", "newton_schulz", "gp_gradient", "expm"],
+    ap.add_argument("--workload", default="product",
+                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt"],
                     help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
                          "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
                          "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072); "
-                         "expm: the truncated exponential series of K (10 terms) on the product workload")
+                         "expm: the truncated exponential series of K (10 terms) on the product workload; "
+                         "ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it")
     return ap.parse_args()
 
 
@@ -267,6 +269,34 @@ def expm_main(args):
     print(json.dumps(out), flush=True)
 
 
+def ns_sqrt_main(args):
+    """(K + 1e-2 I)^{1/2} and its inverse by 12 coupled masked Newton-Schulz iterations
+    (36 products) on the product benchmark's K (N = 131072 cube, exponential kernel)."""
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    w = dict(WORKLOAD, workload="ns_sqrt_cube3", mu=1e-2, iterations=12)
+    n = args.n
+    w["n"] = n
+    print(f"[bench] ns_sqrt: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
+    pts = synth.points_cube(n, w["dim"], w["seed"])
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    A = S.kernel_compress(pat, tree, 0, w["lengthscale"], 1.0 / n)
+    S.axpy(pat, w["mu"], None, 1.0, A)
+    S.ns_sqrt(pat, A, 1)                                              # warm-up
+    (Y, Z, res), ms = _timed(lambda: S.ns_sqrt(pat, A, w["iterations"]))
+    r = res.cpu().tolist()
+    print(f"[bench] ns_sqrt: {ms:.1f} ms, residuals {r[0]:.3e} -> {r[-1]:.3e}", file=sys.stderr, flush=True)
+    out = {"metric": "coupled Newton-Schulz square root and inverse square root on S, 12 iterations (36 products)",
+           "value": 1e3 / ms, "unit": "square roots/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic", "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
+           "ms": ms, "ms_per_product": ms / (3 * w["iterations"]), "residuals": r}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -289,6 +319,8 @@ def main():
         return gp_gradient_main(args)
     if args.workload == "expm":
         return expm_main(args)
+    if args.workload == "ns_sqrt":
+        return ns_sqrt_main(args)
     n = args.n
     w = WORKLOAD
     print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)

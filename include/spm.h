@@ -199,6 +199,23 @@ int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes);
 int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, void *scratch,
                     size_t scratch_bytes, void *stream);
 
+/* Coupled Newton-Schulz iteration for the square root and the inverse square root
+ * of A on S (the matrix square root of Section 4.4, whose errors Section 5.3
+ * reports), FP64, every product formatted:
+ *   Y_0 = A,  Z_0 = I;  for k = 0..iters-1:  W_k = P_S(Z_k Y_k),
+ *   r_k = ||I - W_k||_F / sqrt(n),  T_k = (3I - W_k) / 2,
+ *   Y_{k+1} = P_S(Y_k T_k),  Z_{k+1} = P_S(T_k Z_k).
+ * On the full pattern Y -> A^{1/2} and Z -> A^{-1/2} when ||I - A|| < 1 (for
+ * K + mu I with K scaled by 1/N, any 0 < mu < 1).  A, Y, Z: distinct device F64
+ * value arrays; Y and Z receive Y_iters and Z_iters.  residuals: device array of
+ * iters doubles, or NULL.  scratch: device workspace of at least
+ * spm_ns_sqrt_scratch() bytes (three value arrays).  Asynchronous on the stream;
+ * EINVAL on null or overlapping buffers, a negative iteration count or a short
+ * scratch. */
+int spm_ns_sqrt_scratch(spm_pattern p, size_t *bytes);
+int spm_ns_sqrt(spm_pattern p, const double *A, double *Y, double *Z, int32_t iters, double *residuals,
+                void *scratch, size_t scratch_bytes, void *stream);
+
 /* Masked Newton-Schulz inverse of A (FP64 on S):
  *   X_0 = alpha0 I;  for k = 0..iters-1:  Y_k = P_S(A X_k),  r_k = ||I - Y_k||_F / sqrt(n),
  *   Z_k = 2I - Y_k,  X_{k+1} = P_S(X_k Z_k);  finally r_iters = ||I - P_S(A X_iters)||_F / sqrt(n).

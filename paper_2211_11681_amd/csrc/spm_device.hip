@@ -2054,6 +2054,53 @@ extern "C" int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_
     return SPM_OK;
 }
 
+extern "C" int spm_ns_sqrt_scratch(spm_pattern p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPM_EINVAL, "spm_ns_sqrt_scratch: null pointer");
+    *bytes = 3 * (size_t)p->n_stored * sizeof(double);
+    return SPM_OK;
+}
+
+// Coupled Newton-Schulz iteration for A^{1/2} and A^{-1/2} with formatted products (the
+// square root of Section 4.4, measured in Section 5.3): Y_0 = A, Z_0 = I,
+// T_k = (3I - P_S(Z_k Y_k)) / 2, Y_{k+1} = P_S(Y_k T_k), Z_{k+1} = P_S(T_k Z_k).  Three
+// masked products per iteration; the iterates alternate between the caller's arrays
+// and the scratch.
+extern "C" int spm_ns_sqrt(spm_pattern p, const double *A, double *Y, double *Z, int32_t iters,
+                           double *residuals, void *scratch, size_t scratch_bytes, void *stream)
+{
+    if (!p || !A || !Y || !Z) return fail(SPM_EINVAL, "spm_ns_sqrt: null pointer");
+    if (iters < 0) return fail(SPM_EINVAL, "spm_ns_sqrt: negative iteration count");
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), need = 3 * vb8;
+    if (!scratch || scratch_bytes < need) return fail(SPM_EINVAL, "spm_ns_sqrt: scratch too small");
+    if (overlap(A, Y, vb8) || overlap(A, Z, vb8) || overlap(Y, Z, vb8) || overlap2(A, vb8, scratch, need) ||
+        overlap2(Y, vb8, scratch, need) || overlap2(Z, vb8, scratch, need))
+        return fail(SPM_EINVAL, "spm_ns_sqrt: buffers overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ns = p->n_stored;
+    const double rs = 1.0 / std::sqrt((double)p->n);
+    double *W = static_cast<double *>(scratch);
+    double *y = Y, *z = Z, *yn = W + ns, *zn = yn + ns;
+    int st;
+    SPM_HIP(hipMemcpyAsync(y, A, vb8, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)z);
+    if ((st = spm::launch_axpy(p, SPM_F64, 1.0, nullptr, 1.0, z, s))) return st;
+    for (int32_t k = 0; k < iters; ++k) {
+        if ((st = spm::launch_gemm(p, SPM_F64, z, 0, y, 0, W, s))) return st;          // P_S(Z Y)
+        if (residuals &&
+            (st = spm::launch_reduce(p, 1, SPM_F64, W, nullptr, nullptr, 1.0, 1, rs, residuals + k, s)))
+            return st;
+        if ((st = spm::launch_axpy(p, SPM_F64, 1.5, nullptr, -0.5, W, s))) return st;  // T = (3I - W) / 2
+        if ((st = spm::launch_gemm(p, SPM_F64, y, 0, W, 0, yn, s))) return st;
+        if ((st = spm::launch_gemm(p, SPM_F64, W, 0, z, 0, zn, s))) return st;
+        std::swap(y, yn);
+        std::swap(z, zn);
+    }
+    if (y != Y) SPM_HIP(hipMemcpyAsync(Y, y, vb8, hipMemcpyDeviceToDevice, s));
+    if (z != Z) SPM_HIP(hipMemcpyAsync(Z, z, vb8, hipMemcpyDeviceToDevice, s));
+    return SPM_OK;
+}
+
 extern "C" int spm_newton_schulz_scratch(spm_pattern p, int bulk, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPM_EINVAL, "spm_newton_schulz_scratch: null pointer");

@@ -217,6 +217,18 @@ def fill_outer(pat: Pattern, y, alpha=1.0, out=None) -> torch.Tensor:
     return out
 
 
+def ns_sqrt(pat: Pattern, A: torch.Tensor, iters: int):
+    """Coupled masked Newton-Schulz iteration; returns (Y ~ A^{1/2}, Z ~ A^{-1/2}, residuals)."""
+    need = ctypes.c_size_t()
+    call("spm_ns_sqrt_scratch", pat._h, ctypes.byref(need))
+    scratch = torch.empty((need.value + 7) // 8, dtype=torch.float64, device=A.device)
+    Y, Z = pat.empty("f64"), pat.empty("f64")
+    res = torch.zeros(max(iters, 1), dtype=torch.float64, device=A.device)
+    call("spm_ns_sqrt", pat._h, _ptr(A), _ptr(Y), _ptr(Z), int(iters), _ptr(res), _ptr(scratch),
+         scratch.numel() * 8, _stream())
+    return Y, Z, res[:iters]
+
+
 def expm_taylor(pat: Pattern, A: torch.Tensor, terms: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """sum_{j <= terms} A^j / j! on S by Horner's rule with formatted products (FP64)."""
     need = ctypes.c_size_t()

@@ -297,3 +297,23 @@ def test_expm_taylor_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell):
     # no terms: the identity, exactly
     E0 = S.expm_taylor(pat, K, 0)
     assert np.array_equal(pat.values_to_csr(E0).cpu().numpy(), np.eye(n)[mask])
+
+
+@pytest.mark.parametrize("kind,n,leaf,q,eta,seed,p,ell", [("cube3", 4096, 32, 1, 1.0, 2, 2, 0.2),
+                                                          ("cube2", 2048, 16, 1, 1.6, 1, 1, 0.5)])
+def test_ns_sqrt_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell):
+    # coupled masked Newton-Schulz square root of A = K^eta + 1e-2 I, 12 iterations
+    print(f"case: ns_sqrt {kind} n={n} leaf={leaf} q={q} eta={eta} matern p={p} l={ell}", flush=True)
+    pr = oracle_problem(kind, n, leaf, q, eta, seed, p, ell)
+    pat = S.Pattern.from_csr(n, pr["rp"], pr["col"], pr["basis"].cluster_start)
+    mask = pr["mask"]
+    a = np.where(mask, pr["ks"], 0.0) + 1e-2 * np.eye(n)
+    A = pat.values_from_csr(to_dev(a[mask]))
+    Y, Z, res = S.ns_sqrt(pat, A, 12)
+    y_ref, z_ref, res_ref = ops.ns_sqrt(a, mask, 12)
+    ey = relerr(pat.values_to_csr(Y).cpu().numpy(), y_ref[mask])
+    ez = relerr(pat.values_to_csr(Z).cpu().numpy(), z_ref[mask])
+    print(f"ns_sqrt: Y error {ey:.3e}, Z error {ez:.3e}, residual {float(res[-1]):.3e} (oracle {res_ref[-1]:.3e})")
+    assert ey < TOL64 and ez < TOL64
+    r = res.cpu().numpy()
+    assert np.all(np.abs(r - np.array(res_ref)) <= 1e-12 * np.maximum(np.array(res_ref), 1e-3))
