@@ -243,6 +243,7 @@ def gp_gradient_main(args):
 def expm_main(args):
     """exp(K) by its power series cut after 10 terms, Horner's rule with formatted
     products, on the product benchmark's K (N = 131072 cube, exponential kernel)."""
+    import numpy as np
     import torch
 
     import synth
@@ -262,16 +263,27 @@ def expm_main(args):
     _, ms = _timed(lambda: [S.expm_taylor(pat, K, w["terms"], out=E) for _ in range(reps)])
     ms /= reps
     print(f"[bench] expm: {ms:.1f} ms for {w['terms']} terms", file=sys.stderr, flush=True)
+    # the paper's error measure (Section 5.3): e_F(exp(K) - E) with exp(K) X from 30 terms
+    # of the series applied to a uniform block X of 10 columns
+    X = torch.from_numpy(synth.uniform(91, np.arange(10 * n)).reshape(10, n)).cuda()
+    ref, t = X.clone(), X
+    for j in range(1, 31):
+        t = S.spmm(pat, K, t) / j
+        ref += t
+    (approx,), ms_spmm = _timed(lambda: (S.spmm(pat, E, X),))
+    e_f = float(torch.linalg.norm(ref - approx) / torch.linalg.norm(X))
+    print(f"[bench] expm: e_F(exp(K) - E) = {e_f:.3e}", file=sys.stderr, flush=True)
     out = {"metric": "truncated exponential series exp(K) on S, 10 terms (10 masked products)",
            "value": 1e3 / ms, "unit": "exponentials/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
            "data": "synthetic", "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
-           "ms": ms, "ms_per_product": ms / w["terms"]}
+           "ms": ms, "ms_per_product": ms / w["terms"], "e_F_vs_30_term_series": e_f, "ms_spmm_10_columns": ms_spmm}
     print(json.dumps(out), flush=True)
 
 
 def ns_sqrt_main(args):
     """(K + 1e-2 I)^{1/2} and its inverse by 12 coupled masked Newton-Schulz iterations
     (36 products) on the product benchmark's K (N = 131072 cube, exponential kernel)."""
+    import numpy as np
     import torch
 
     import synth
@@ -290,10 +302,18 @@ def ns_sqrt_main(args):
     (Y, Z, res), ms = _timed(lambda: S.ns_sqrt(pat, A, w["iterations"]))
     r = res.cpu().tolist()
     print(f"[bench] ns_sqrt: {ms:.1f} ms, residuals {r[0]:.3e} -> {r[-1]:.3e}", file=sys.stderr, flush=True)
+    # the paper's measure (Section 5.3): e_F(Y Y - A), and e_F(Z Y - I) for the inverse
+    X = torch.from_numpy(synth.uniform(92, np.arange(10 * n)).reshape(10, n)).cuda()
+    YX = S.spmm(pat, Y, X)
+    nx = torch.linalg.norm(X)
+    e_sq = float(torch.linalg.norm(S.spmm(pat, Y, YX) - S.spmm(pat, A, X)) / nx)
+    e_inv = float(torch.linalg.norm(S.spmm(pat, Z, YX) - X) / nx)
+    print(f"[bench] ns_sqrt: e_F(YY - A) = {e_sq:.3e}, e_F(ZY - I) = {e_inv:.3e}", file=sys.stderr, flush=True)
     out = {"metric": "coupled Newton-Schulz square root and inverse square root on S, 12 iterations (36 products)",
            "value": 1e3 / ms, "unit": "square roots/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
            "data": "synthetic", "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
-           "ms": ms, "ms_per_product": ms / (3 * w["iterations"]), "residuals": r}
+           "ms": ms, "ms_per_product": ms / (3 * w["iterations"]), "residuals": r,
+           "e_F_YY_minus_A": e_sq, "e_F_ZY_minus_I": e_inv}
     print(json.dumps(out), flush=True)
 
 

@@ -199,6 +199,14 @@ int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes);
 int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, void *scratch,
                     size_t scratch_bytes, void *stream);
 
+/* Y = A X: an S-matrix A (device F64 value array) times a dense block X of r
+ * columns, the product of the paper's error estimator e_F(A) = ||A X||_F / ||X||_F
+ * (Section 5.1).  X and Y: device F64, column-major n x r (column j at offset
+ * j n), rows in basis order; Y must not overlap A or X.  Block row nu of Y sums the
+ * tiles of block row nu in storage order (deterministic).  r = 0 does nothing.
+ * Asynchronous on the stream; EINVAL on null or overlapping buffers or r < 0. */
+int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double *Y, void *stream);
+
 /* Coupled Newton-Schulz iteration for the square root and the inverse square root
  * of A on S (the matrix square root of Section 4.4, whose errors Section 5.3
  * reports), FP64, every product formatted:

@@ -23,6 +23,8 @@
 * ``expm_series_apply``: exp(A) X by the series applied to a block X without
   any pattern (the paper's reference for its exponential errors, Section 5.3,
   30 terms).
+* ``spmm``: an S-matrix (zero outside the pattern) times a dense block, the
+  product inside the error estimator e_F (Section 5.1).
 * ``ns_sqrt``: coupled Newton-Schulz iteration for A^{1/2} and A^{-1/2} with
   every product formatted: Y_0 = A, Z_0 = I, T_k = (3I - P_S(Z_k Y_k)) / 2,
   Y_{k+1} = P_S(Y_k T_k), Z_{k+1} = P_S(T_k Z_k).  The paper computes the
@@ -157,3 +159,8 @@ def ns_sqrt(a: np.ndarray, mask: np.ndarray, iters: int):
         t = np.where(mask, 0.5 * (3.0 * eye - w), 0.0)
         y, z = masked_product(y, t, mask), masked_product(t, z, mask)
     return y, z, res
+
+
+def spmm(a: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """A X for an S-matrix A held dense (zero outside S) and a dense block X."""
+    return a @ x

@@ -1545,6 +1545,35 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
     }
 }
 
+// Y = A X for an S-matrix A (tile layout) and a dense block X of r columns (column-major,
+// leading dimension n, basis order), the product behind the paper's error estimator
+// e_F (Section 5.1): block row nu of Y is the sum over the tiles of block row nu of
+// A_{nu mu} X_mu.  One workgroup per cluster; each thread owns outputs (row, column) of
+// the block row and adds the tiles in storage order (a fixed order).
+__global__ __launch_bounds__(128) void k_spmm(int32_t nc, int64_t n, int32_t r, const int64_t *__restrict__ blk_rp,
+                                              const int32_t *__restrict__ tile_col,
+                                              const int64_t *__restrict__ tile_off, const int32_t *__restrict__ nfun,
+                                              const int64_t *__restrict__ cstart, const double *__restrict__ A,
+                                              const double *__restrict__ X, double *__restrict__ Y)
+{
+    const int c = blockIdx.x;
+    if (c >= nc) return;
+    const int nr = nfun[c];
+    const int64_t row0 = cstart[c];
+    for (int o = threadIdx.x; o < nr * r; o += blockDim.x) {
+        const int i = o % nr, col = o / nr;
+        const double *xc = X + (int64_t)col * n;
+        double acc = 0.0;
+        for (int64_t t = blk_rp[c]; t < blk_rp[c + 1]; ++t) {
+            const int mu = tile_col[t], nm = nfun[mu];
+            const double *a = A + tile_off[t] + i;
+            const double *x = xc + cstart[mu];
+            for (int k = 0; k < nm; ++k) acc = fma(a[(int64_t)k * nr], x[k], acc);
+        }
+        Y[(int64_t)col * n + row0 + i] = acc;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
                                                    const int32_t *__restrict__ tile_row,
@@ -2051,6 +2080,20 @@ extern "C" int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_
         std::swap(cur, oth);
     }
     if (cur != E) SPM_HIP(hipMemcpyAsync(E, cur, vb8, hipMemcpyDeviceToDevice, s));
+    return SPM_OK;
+}
+
+extern "C" int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double *Y, void *stream)
+{
+    if (!p || !A || !X || !Y) return fail(SPM_EINVAL, "spm_spmm: null pointer");
+    if (r < 0) return fail(SPM_EINVAL, "spm_spmm: negative column count");
+    if (r == 0 || p->nc == 0) return SPM_OK;
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), pb = (size_t)p->n * r * sizeof(double);
+    if (overlap2(X, pb, Y, pb) || overlap2(A, vb8, Y, pb)) return fail(SPM_EINVAL, "spm_spmm: buffers overlap");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_spmm, dim3((unsigned)p->nc), dim3(128), 0, s, p->nc, (int64_t)p->n, r, p->d_blk_rp.ptr,
+                       p->d_tile_col.ptr, p->d_tile_off.ptr, p->d_nfun.ptr, p->d_cstart.ptr, A, X, Y);
+    SPM_HIP(hipGetLastError());
     return SPM_OK;
 }
 

@@ -217,6 +217,15 @@ def fill_outer(pat: Pattern, y, alpha=1.0, out=None) -> torch.Tensor:
     return out
 
 
+def spmm(pat: Pattern, A: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """A X for a block X of shape (r, n) (row j = column j of the n x r block, basis order)."""
+    assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == pat.n
+    X = X.contiguous()
+    Y = torch.empty_like(X)
+    call("spm_spmm", pat._h, _ptr(A), _ptr(X), int(X.shape[0]), _ptr(Y), _stream())
+    return Y
+
+
 def ns_sqrt(pat: Pattern, A: torch.Tensor, iters: int):
     """Coupled masked Newton-Schulz iteration; returns (Y ~ A^{1/2}, Z ~ A^{-1/2}, residuals)."""
     need = ctypes.c_size_t()

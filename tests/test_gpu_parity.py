@@ -317,3 +317,17 @@ def test_ns_sqrt_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell):
     assert ey < TOL64 and ez < TOL64
     r = res.cpu().numpy()
     assert np.all(np.abs(r - np.array(res_ref)) <= 1e-12 * np.maximum(np.array(res_ref), 1e-3))
+
+
+def test_spmm_vs_oracle(S, cfg1):
+    # S-matrix times a dense block of 10 columns (uniform entries, as in the paper's e_F)
+    print("case: spmm cfg1 r=10", flush=True)
+    pat, mask, n = cfg1["pat"], cfg1["mask"], cfg1["n"]
+    a = np.where(mask, cfg1["ks"], 0.0)
+    A = pat.values_from_csr(to_dev(a[mask]))
+    x = synth.uniform(77, np.arange(10 * n)).reshape(10, n)
+    Y = S.spmm(pat, A, to_dev(x))
+    ref = ops.spmm(a, x.T).T
+    err = relerr(Y.cpu().numpy(), ref)
+    print(f"spmm: relative Frobenius error vs oracle {err:.3e}")
+    assert err < TOL64

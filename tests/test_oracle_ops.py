@@ -290,3 +290,19 @@ def test_ns_sqrt_on_compressed_kernel(cfg1_setup):
     print(f"residuals {res[0]:.2e} -> {res[-1]:.2e}; e_F(YY - A) = {e_sq:.2e}")
     assert res[-1] < 1e-3 * res[0]
     assert e_sq < 1e-4
+
+
+def test_spmm_brute_force_tiny():
+    # the oracle's S-matrix times block against an explicit triple loop over the pattern
+    rng = np.random.default_rng(9)
+    n, r = 9, 3
+    mask = rng.uniform(size=(n, n)) < 0.4
+    a = np.where(mask, rng.standard_normal((n, n)), 0.0)
+    x = rng.standard_normal((n, r))
+    y = np.zeros((n, r))
+    for i in range(n):
+        for k in range(n):
+            if mask[i, k]:
+                for c in range(r):
+                    y[i, c] += a[i, k] * x[k, c]
+    assert np.allclose(ops.spmm(a, x), y, rtol=1e-14, atol=1e-14)
