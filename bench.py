@@ -273,10 +273,15 @@ def expm_main(args):
     (approx,), ms_spmm = _timed(lambda: (S.spmm(pat, E, X),))
     e_f = float(torch.linalg.norm(ref - approx) / torch.linalg.norm(X))
     print(f"[bench] expm: e_F(exp(K) - E) = {e_f:.3e}", file=sys.stderr, flush=True)
+    # fast samplet transform of the 10 probe vectors and back (point order <-> basis order)
+    (Wt,), ms_fst = _timed(lambda: (S.fst(tree, X),))
+    (Xb,), ms_ifst = _timed(lambda: (S.fst(tree, Wt, inverse=True),))
+    fst_rt = float(torch.linalg.norm(Xb - X) / torch.linalg.norm(X))
     out = {"metric": "truncated exponential series exp(K) on S, 10 terms (10 masked products)",
            "value": 1e3 / ms, "unit": "exponentials/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
            "data": "synthetic", "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
-           "ms": ms, "ms_per_product": ms / w["terms"], "e_F_vs_30_term_series": e_f, "ms_spmm_10_columns": ms_spmm}
+           "ms": ms, "ms_per_product": ms / w["terms"], "e_F_vs_30_term_series": e_f, "ms_spmm_10_columns": ms_spmm,
+           "ms_fst_10_vectors": ms_fst, "ms_inverse_fst_10_vectors": ms_ifst, "fst_round_trip_rel_err": fst_rt}
     print(json.dumps(out), flush=True)
 
 

@@ -199,6 +199,15 @@ int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes);
 int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, void *scratch,
                     size_t scratch_bytes, void *stream);
 
+/* Fast samplet transform of r vectors (Section 3.2, the transform T of
+ * K^Sigma = T K T^T): inverse = 0 gives Y = T X with X in the points' original
+ * order and Y in basis order; inverse = 1 gives Y = T^T X (T is orthogonal) with X
+ * in basis order and Y in the original order.  X, Y: distinct device F64 arrays,
+ * r x n row-major (vector j at offset j n).  Uses a temporary device buffer of r n
+ * doubles and the tree's transform tables (uploaded per call) and synchronises the
+ * stream before returning.  EINVAL on null or overlapping buffers or r < 0. */
+int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_t inverse, void *stream);
+
 /* Y = A X: an S-matrix A (device F64 value array) times a dense block X of r
  * columns, the product of the paper's error estimator e_F(A) = ||A X||_F / ||X||_F
  * (Section 5.1).  X and Y: device F64, column-major n x r (column j at offset

@@ -23,6 +23,9 @@
 * ``expm_series_apply``: exp(A) X by the series applied to a block X without
   any pattern (the paper's reference for its exponential errors, Section 5.3,
   30 terms).
+* ``fst`` / ``ifst``: the samplet transform of vectors, omega = T x with x in
+  the points' original order (Section 3.2: the rows of T are the samplets'
+  coefficient vectors over the points), and its inverse T^T (T is orthogonal).
 * ``spmm``: an S-matrix (zero outside the pattern) times a dense block, the
   product inside the error estimator e_F (Section 5.1).
 * ``ns_sqrt``: coupled Newton-Schulz iteration for A^{1/2} and A^{-1/2} with
@@ -164,3 +167,15 @@ def ns_sqrt(a: np.ndarray, mask: np.ndarray, iters: int):
 def spmm(a: np.ndarray, x: np.ndarray) -> np.ndarray:
     """A X for an S-matrix A held dense (zero outside S) and a dense block X."""
     return a @ x
+
+
+def fst(basis, x: np.ndarray) -> np.ndarray:
+    """T x for x of shape (n,) or (n, r) in the points' original order."""
+    return basis.sparse_T() @ x[basis.tree.perm]
+
+
+def ifst(basis, w: np.ndarray) -> np.ndarray:
+    """T^T w for w in basis order, returned in the points' original order."""
+    out = np.empty_like(w)
+    out[basis.tree.perm] = basis.sparse_T().T @ w
+    return out

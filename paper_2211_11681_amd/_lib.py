@@ -40,6 +40,7 @@ SIGNATURES = {
     "spm_quadform": [_P, _P, _P, _P, _P],
     "spm_fill_outer": [_P, _D, _P, _P, _P],
     "spm_spmm": [_P, _P, _P, _I32, _P, _P],
+    "spm_fst": [_P, _P, _I32, _P, _I32, _P],
     "spm_ns_sqrt_scratch": [_P, _P],
     "spm_ns_sqrt": [_P, _P, _P, _P, _I32, _P, _P, ctypes.c_size_t, _P],
     "spm_expm_taylor_scratch": [_P, _P],

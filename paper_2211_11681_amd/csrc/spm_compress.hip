@@ -115,6 +115,53 @@ __global__ __launch_bounds__(64) void k_rowtr(double *__restrict__ R, int64_t n,
     }
 }
 
+// Inverse of the column transform for one tree level (levels run root first): the
+// cluster's outputs, read at its slots, are mapped back by Q (Q is orthogonal and the
+// forward step applies Q^T), writing input i to slot i.
+__global__ __launch_bounds__(64) void k_coltr_t(double *__restrict__ W, int64_t rows, int64_t n,
+                                                const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
+                                                const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
+                                                const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots)
+{
+    __shared__ double sQ[kMaxIn * kMaxIn];
+    __shared__ double sOut[kMaxIn * 64];
+    const int c = clist[blockIdx.x];
+    const int m = nin[c];
+    const double *Q = qmat + qoff[c];
+    for (int e = threadIdx.x; e < m * m; e += 64) sQ[e] = Q[e];
+    const int64_t *sl = slots + slotoff[c];
+    const int64_t r = (int64_t)blockIdx.y * 64 + threadIdx.x;
+    __syncthreads();
+    if (r >= rows) return;
+    double *row = W + r * n;
+    for (int k = 0; k < m; ++k) sOut[k * 64 + threadIdx.x] = row[sl[k]];
+    for (int i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) acc = fma(sQ[k * m + i], sOut[k * 64 + threadIdx.x], acc);
+        row[sl[i]] = acc;
+    }
+}
+
+// Row-wise permutations of an r x n block: gather out[j][k] = in[j][idx[k]], scatter
+// out[j][idx[k]] = in[j][k] (idx a permutation of 0 .. n-1).
+__global__ void k_gather_rows(int64_t n, int64_t total, const int64_t *__restrict__ idx, const double *__restrict__ in,
+                              double *__restrict__ out)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / n, k = e - j * n;
+        out[e] = in[j * n + idx[k]];
+    }
+}
+
+__global__ void k_scatter_rows(int64_t n, int64_t total, const int64_t *__restrict__ idx, const double *__restrict__ in,
+                               double *__restrict__ out)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / n, k = e - j * n;
+        out[j * n + idx[k]] = in[e];
+    }
+}
+
 // Samplet rows of block rows -> tiles.  Element (i, j) of tile (r, c) is the value of
 // basis row cstart[r] + i (output kb[r] + i of cluster r) at basis column cstart[c] + j.
 __global__ void k_extract(double *__restrict__ vals, const double *__restrict__ R, int64_t n, int64_t base,
@@ -347,5 +394,70 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
         if ((st = extract(dU.p, 0, tl_up[i].first, tl_up[i].second, durloff.p, durows.p))) return st;
     }
     SPM_HIP(hipStreamSynchronize(s));
+    return SPM_OK;
+}
+
+// Fast samplet transform of r vectors (Section 3.2): Y = T X with X in the points'
+// original order and Y in basis order, or the inverse X = T^T Y.  The two-scale
+// transform is applied level by level in place on a tree-ordered copy, as in the
+// column transform of the compression above.
+extern "C" int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_t inverse, void *stream)
+{
+    if (!t || !X || !Y) return fail(SPM_EINVAL, "spm_fst: null pointer");
+    if (r < 0) return fail(SPM_EINVAL, "spm_fst: negative vector count");
+    const int64_t n = t->n, total = (int64_t)r * n;
+    if (r == 0 || n == 0) return SPM_OK;
+    {
+        const char *x0 = reinterpret_cast<const char *>(X), *y0 = reinterpret_cast<const char *>(Y);
+        const size_t b = (size_t)total * sizeof(double);
+        if (x0 < y0 + b && y0 < x0 + b) return fail(SPM_EINVAL, "spm_fst: X and Y overlap");
+    }
+    const int nc = t->nc, depth = t->depth;
+    for (int c = 0; c < nc; ++c)
+        if (t->nin[c] > kMaxIn) return fail(SPM_EUNSUPPORTED, "spm_fst: more than 64 inputs in one cluster");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> kb(nc);
+    for (int c = 0; c < nc; ++c) kb[c] = c == 0 ? 0 : t->nscal[c];
+    std::vector<int64_t> sob(n);                       // basis index -> slot of its coefficient
+    for (int c = 0; c < nc; ++c)
+        for (int k = kb[c]; k < t->nin[c]; ++k) sob[t->cstart[c] + (k - kb[c])] = t->slots[t->slotoff[c] + k];
+    std::vector<std::vector<int32_t>> bylevel(depth + 1);
+    for (int c = 0; c < nc; ++c) bylevel[t->level[c]].push_back(c);
+    std::vector<int32_t> clist;
+    std::vector<std::pair<int64_t, int64_t>> lvl(depth + 1);
+    for (int l = 0; l <= depth; ++l) {
+        lvl[l] = {(int64_t)clist.size(), (int64_t)bylevel[l].size()};
+        clist.insert(clist.end(), bylevel[l].begin(), bylevel[l].end());
+    }
+    Dev<double> dq, dW;
+    Dev<int32_t> dnin, dcl;
+    Dev<int64_t> dqoff, dsloff, dslots, dsob, dperm;
+    int st;
+    if ((st = up(dq, t->qmat, s)) || (st = up(dnin, t->nin, s)) || (st = up(dqoff, t->qoff, s)) ||
+        (st = up(dsloff, t->slotoff, s)) || (st = up(dslots, t->slots, s)) || (st = up(dsob, sob, s)) ||
+        (st = up(dperm, t->perm, s)) || (st = up(dcl, clist, s)))
+        return st;
+    if (hipMalloc(&dW.p, (size_t)total * sizeof(double)) != hipSuccess) { dW.p = nullptr; return fail(SPM_ENOMEM, "spm_fst: work buffer"); }
+    const unsigned g1 = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+    auto level = [&](int l, bool tr) {
+        auto [o, cnt] = lvl[l];
+        if (cnt == 0) return;
+        dim3 g((unsigned)cnt, (unsigned)((r + 63) / 64));
+        if (tr)
+            hipLaunchKernelGGL(k_coltr_t, g, dim3(64), 0, s, dW.p, (int64_t)r, n, dcl.p + o, dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p);
+        else
+            hipLaunchKernelGGL(k_coltr, g, dim3(64), 0, s, dW.p, (int64_t)r, n, dcl.p + o, dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p);
+    };
+    if (!inverse) {
+        hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, dperm.p, X, dW.p);   // tree order
+        for (int l = depth; l >= 0; --l) level(l, false);
+        hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, dsob.p, dW.p, Y);    // basis order
+    } else {
+        hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, s, n, total, dsob.p, X, dW.p);
+        for (int l = 0; l <= depth; ++l) level(l, true);
+        hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, s, n, total, dperm.p, dW.p, Y);   // original order
+    }
+    SPM_HIP(hipGetLastError());
+    SPM_HIP(hipStreamSynchronize(s));                 // the tables and the work buffer are freed on return
     return SPM_OK;
 }

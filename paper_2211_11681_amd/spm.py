@@ -217,6 +217,16 @@ def fill_outer(pat: Pattern, y, alpha=1.0, out=None) -> torch.Tensor:
     return out
 
 
+def fst(tree: Tree, X: torch.Tensor, inverse: bool = False) -> torch.Tensor:
+    """Fast samplet transform of the rows of X (shape (r, n)): T x (original point order ->
+    basis order), or T^T x with inverse=True."""
+    assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == tree.n
+    X = X.contiguous()
+    Y = torch.empty_like(X)
+    call("spm_fst", tree._h, _ptr(X), int(X.shape[0]), _ptr(Y), int(bool(inverse)), _stream())
+    return Y
+
+
 def spmm(pat: Pattern, A: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """A X for a block X of shape (r, n) (row j = column j of the n x r block, basis order)."""
     assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == pat.n

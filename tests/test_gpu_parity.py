@@ -331,3 +331,20 @@ def test_spmm_vs_oracle(S, cfg1):
     err = relerr(Y.cpu().numpy(), ref)
     print(f"spmm: relative Frobenius error vs oracle {err:.3e}")
     assert err < TOL64
+
+
+def test_fst_vs_oracle(S):
+    # fast samplet transform of 3 vectors (original point order -> basis order) and back
+    print("case: fst cube3 n=3000 leaf 32 q 1", flush=True)
+    n = 3000
+    pts = synth.workload_points("cube3", n, 4)
+    t = S.Tree(pts, 32, 1)
+    ot = tree.build_tree(pts, 32)
+    ob = samplets.build_samplets(ot, 1)
+    x = 2 * synth.uniform(78, np.arange(3 * n)).reshape(3, n) - 1
+    W = S.fst(t, to_dev(x))
+    ref = ops.fst(ob, x.T).T
+    err = relerr(W.cpu().numpy(), ref)
+    back = S.fst(t, W, inverse=True).cpu().numpy()
+    print(f"fst: relative error vs oracle {err:.3e}, round trip {relerr(back, x):.3e}")
+    assert err < TOL64 and relerr(back, x) < TOL64

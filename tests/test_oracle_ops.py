@@ -306,3 +306,23 @@ def test_spmm_brute_force_tiny():
                 for c in range(r):
                     y[i, c] += a[i, k] * x[k, c]
     assert np.allclose(ops.spmm(a, x), y, rtol=1e-14, atol=1e-14)
+
+
+def test_fst_orthogonal_and_vanishing_moments():
+    # T is orthogonal (norms kept, T^T inverts it) and samplets have vanishing moments:
+    # a polynomial of degree <= q has coefficients only on the root's scaling functions.
+    import synth
+    from oracle import samplets, tree
+    pts = synth.points_cube(700, 2, 21)
+    ot = tree.build_tree(pts, 12)
+    ob = samplets.build_samplets(ot, 1)
+    rng = np.random.default_rng(10)
+    x = rng.standard_normal((700, 3))
+    w = ops.fst(ob, x)
+    assert np.allclose(np.linalg.norm(w, axis=0), np.linalg.norm(x, axis=0), rtol=1e-13)
+    assert np.allclose(ops.ifst(ob, w), x, rtol=0, atol=1e-13)
+    poly = 0.3 + 1.7 * pts[:, 0] - 0.9 * pts[:, 1]
+    wp = ops.fst(ob, poly)
+    assert int(ob.cluster_start[1]) >= ob.m  # the root's scaling functions come first
+    assert np.max(np.abs(wp[ob.m:])) <= 1e-11 * np.linalg.norm(poly)
+    assert np.linalg.norm(wp[:ob.m]) == pytest.approx(np.linalg.norm(poly), rel=1e-12)
