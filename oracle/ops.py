@@ -26,6 +26,15 @@
 * ``fst`` / ``ifst``: the samplet transform of vectors, omega = T x with x in
   the points' original order (Section 3.2: the rows of T are the samplets'
   coefficient vectors over the points), and its inverse T^T (T is orthogonal).
+* ``contour_invsqrt_rule`` / ``contour_invsqrt``: A^{-1/2} by the quadrature of
+  Section 4.4 (eq. ContInt): A^{-1/2} ~ sum_k c_k (A + w_k^2 I)^{-1} with
+  w_k = sqrt(m) sn(t_k)/cn(t_k), c_k = 2 Kq sqrt(m) dn(t_k) / (pi n cn(t_k)^2),
+  t_k = Kq (k - 1/2) / n, Jacobi functions of parameter 1 - m/M, [m, M] the
+  spectral bounds.  It is the midpoint rule for
+  A^{-1/2} = (2/pi) int_0^inf (A + w^2 I)^{-1} dw after w = sqrt(m) sn/cn, which
+  maps t in (0, Kq) onto w in (0, inf); so Kq is the quarter period, the complete
+  elliptic integral of the first kind (the printed "second kind" is read as a
+  garble).  Each shifted inverse is the masked Newton-Schulz iteration.
 * ``spmm``: an S-matrix (zero outside the pattern) times a dense block, the
   product inside the error estimator e_F (Section 5.1).
 * ``ns_sqrt``: coupled Newton-Schulz iteration for A^{1/2} and A^{-1/2} with
@@ -178,4 +187,28 @@ def ifst(basis, w: np.ndarray) -> np.ndarray:
     """T^T w for w in basis order, returned in the points' original order."""
     out = np.empty_like(w)
     out[basis.tree.perm] = basis.sparse_T().T @ w
+    return out
+
+
+def contour_invsqrt_rule(m_lo: float, m_hi: float, nodes: int):
+    """Shifts w_k^2 and weights c_k of the quadrature for A^{-1/2} on [m_lo, m_hi]."""
+    from scipy.special import ellipj, ellipk
+    k2 = 1.0 - m_lo / m_hi
+    kq = ellipk(k2)
+    t = kq * (np.arange(1, nodes + 1) - 0.5) / nodes
+    sn, cn, dn, _ = ellipj(t, k2)
+    w = np.sqrt(m_lo) * sn / cn
+    c = 2.0 * kq * np.sqrt(m_lo) / (np.pi * nodes) * dn / cn ** 2
+    return w ** 2, c
+
+
+def contour_invsqrt(a: np.ndarray, mask: np.ndarray, m_lo: float, m_hi: float, nodes: int, ns_iters: int):
+    """sum_k c_k X_k with X_k the masked Newton-Schulz inverse of A + w_k^2 I
+    (X_0 = 2 / (m_lo + m_hi + 2 w_k^2) I, the inverse of the shifted bounds' midpoint)."""
+    n = a.shape[0]
+    eye = np.eye(n)
+    out = np.zeros_like(a)
+    for w2, c in zip(*contour_invsqrt_rule(m_lo, m_hi, nodes)):
+        x, _, _ = newton_schulz(np.where(mask, a + w2 * eye, 0.0), mask, ns_iters, 2.0 / (m_lo + m_hi + 2.0 * w2))
+        out = out + c * x
     return out

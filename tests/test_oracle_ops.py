@@ -326,3 +326,38 @@ def test_fst_orthogonal_and_vanishing_moments():
     assert int(ob.cluster_start[1]) >= ob.m  # the root's scaling functions come first
     assert np.max(np.abs(wp[ob.m:])) <= 1e-11 * np.linalg.norm(poly)
     assert np.linalg.norm(wp[:ob.m]) == pytest.approx(np.linalg.norm(poly), rel=1e-12)
+
+
+def test_contour_rule_scalar_convergence():
+    # The rule integrates lambda^{-1/2} = (2/pi) int_0^inf dw / (lambda + w^2) for every
+    # lambda in [m, M], with an error falling exponentially in the number of nodes.
+    m, M = 1e-2, 1.0
+    lam = np.geomspace(m, M, 200)
+    errs = []
+    for nodes in (4, 8, 16):
+        w2, c = ops.contour_invsqrt_rule(m, M, nodes)
+        approx = (c[None, :] / (lam[:, None] + w2[None, :])).sum(axis=1)
+        errs.append(np.max(np.abs(approx * np.sqrt(lam) - 1.0)))
+    assert errs[0] > 10 * errs[1] > 100 * errs[2] and errs[2] < 1e-8
+    # the printed "second kind" in place of the quarter period does not converge
+    from scipy.special import ellipe, ellipj
+    k2 = 1 - m / M
+    t = ellipe(k2) * (np.arange(1, 17) - 0.5) / 16
+    sn, cn, dn, _ = ellipj(t, k2)
+    c2 = 2 * ellipe(k2) * np.sqrt(m) / (np.pi * 16) * dn / cn ** 2
+    bad = (c2[None, :] / (lam[:, None] + (m * sn ** 2 / cn ** 2)[None, :])).sum(axis=1)
+    assert np.max(np.abs(bad * np.sqrt(lam) - 1.0)) > 1e-2
+
+
+def test_contour_invsqrt_full_pattern_is_library():
+    # S = everything and converged shifted inverses: the library inverse square root,
+    # up to the rule's error (16 nodes on [0.05, 1.5])
+    import scipy.linalg
+    rng = np.random.default_rng(11)
+    n = 30
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(0.05, 1.5, n)
+    a = (q * lam) @ q.T
+    x = ops.contour_invsqrt(a, np.ones((n, n), bool), 0.05, 1.5, 16, 40)
+    ref = np.linalg.inv(scipy.linalg.sqrtm(a).real)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
