@@ -51,12 +51,14 @@ def parse():
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
     ap.add_argument("--workload", default="product",
-                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt"],
+                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour"],
                     help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
                          "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
                          "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072); "
                          "expm: the truncated exponential series of K (10 terms) on the product workload; "
-                         "ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it")
+                         "ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it; "
+                         "contour: (K + 1e-2 I)^{-1/2} on it by a 6-node contour quadrature with 12 masked "
+                         "Newton-Schulz iterations per shifted inverse")
     return ap.parse_args()
 
 
@@ -322,11 +324,56 @@ def ns_sqrt_main(args):
     print(json.dumps(out), flush=True)
 
 
+def contour_main(args):
+    """(K + 1e-2 I)^{-1/2} by the contour quadrature of Section 4.4: 6 nodes, each a shifted
+    inverse by 12 masked Newton-Schulz iterations (25 products per node), on the product
+    benchmark's K (N = 131072 cube, exponential kernel)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    w = dict(WORKLOAD, workload="contour_invsqrt_cube3", mu=1e-2, nodes=6, ns_iterations=12)
+    n = args.n
+    w["n"] = n
+    print(f"[bench] contour: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
+    pts = synth.points_cube(n, w["dim"], w["seed"])
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    A = S.kernel_compress(pat, tree, 0, w["lengthscale"], 1.0 / n)
+    S.axpy(pat, w["mu"], None, 1.0, A)
+    # spectral bounds: mu below (K is positive semi-definite), 1.05 x a power-iteration estimate above
+    v = torch.from_numpy(synth.uniform(93, np.arange(n)).reshape(1, n)).cuda()
+    for _ in range(40):
+        v = S.spmm(pat, A, v)
+        lam = float(torch.linalg.norm(v))
+        v = v / lam
+    lo, hi = w["mu"], 1.05 * lam
+    w.update(lam_min=lo, lam_max=hi)
+    S.contour_invsqrt(pat, A, lo, hi, 1, 1)                           # warm-up
+    (Z, res), ms = _timed(lambda: S.contour_invsqrt(pat, A, lo, hi, w["nodes"], w["ns_iterations"]))
+    r = res.cpu().tolist()
+    print(f"[bench] contour: {ms:.1f} ms, node residuals {r}", file=sys.stderr, flush=True)
+    # accuracy on a uniform probe block X of 10 columns: e_F(Z A Z - I)
+    X = torch.from_numpy(synth.uniform(94, np.arange(10 * n)).reshape(10, n)).cuda()
+    e_inv = float(torch.linalg.norm(S.spmm(pat, Z, S.spmm(pat, A, S.spmm(pat, Z, X))) - X) / torch.linalg.norm(X))
+    print(f"[bench] contour: e_F(ZAZ - I) = {e_inv:.3e}", file=sys.stderr, flush=True)
+    products = w["nodes"] * (2 * w["ns_iterations"] + 1)
+    out = {"metric": "inverse square root on S by the contour quadrature (6 nodes x 12 Newton-Schulz iterations)",
+           "value": 1e3 / ms, "unit": "inverse square roots/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
+           "ms": ms, "products": products, "ms_per_product": ms / products, "node_residuals": r,
+           "e_F_ZAZ_minus_I": e_inv}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the product is not sharded "
-              f"across GPUs in this build.", file=sys.stderr)
+              f"across GPUs.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -346,6 +393,8 @@ def main():
         return expm_main(args)
     if args.workload == "ns_sqrt":
         return ns_sqrt_main(args)
+    if args.workload == "contour":
+        return contour_main(args)
     n = args.n
     w = WORKLOAD
     print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)

@@ -248,6 +248,30 @@ int spm_newton_schulz(spm_pattern p, const double *A, double *X, int32_t iters, 
                       int bulk, double alpha0, double *residuals, double *const *checkpoints,
                       void *scratch, size_t scratch_bytes, void *stream);
 
+/* Quadrature rule of the contour integral for the inverse square root (Section 4.4,
+ * eq. ContInt): A^{-1/2} ~ sum_k c[k] (A + w2[k] I)^{-1} for a spectrum in
+ * [lam_min, lam_max], k = 0..nodes-1, with w_k = sqrt(lam_min) sn(t_k)/cn(t_k),
+ * c_k = 2 Kq sqrt(lam_min) dn(t_k) / (pi nodes cn(t_k)^2), t_k = Kq (k + 1/2) / nodes,
+ * Jacobi functions of parameter 1 - lam_min/lam_max and Kq their quarter period
+ * (the complete elliptic integral of the first kind).  Host arrays w2[nodes],
+ * c[nodes]; host only (no device work).  EINVAL unless 0 < lam_min <= lam_max
+ * (finite) and nodes >= 1. */
+int spm_contour_rule(double lam_min, double lam_max, int32_t nodes, double *w2, double *c);
+
+/* out = sum_k c_k X_k ~ A^{-1/2} (FP64 on S), X_k the masked Newton-Schulz inverse
+ * (spm_newton_schulz, all FP64, ns_iters iterations, X_0 = 2/(lam_min + lam_max +
+ * 2 w_k^2) I) of A + w_k^2 I, with the rule of spm_contour_rule on [lam_min, lam_max].
+ * A^{1/2} follows as P_S(A out).  out: device F64 value array distinct from A.
+ * residuals: device array of `nodes` doubles (the final Newton-Schulz residual of
+ * each shifted inverse), or NULL.  scratch: device workspace of at least
+ * spm_contour_invsqrt_scratch() bytes.  Synchronises the stream once per node (as
+ * spm_newton_schulz does); ENOTCONV when a shifted inverse's residual is not finite,
+ * EINVAL on bad arguments. */
+int spm_contour_invsqrt_scratch(spm_pattern p, int32_t ns_iters, size_t *bytes);
+int spm_contour_invsqrt(spm_pattern p, const double *A, double lam_min, double lam_max, int32_t nodes,
+                        int32_t ns_iters, double *out, double *residuals, void *scratch, size_t scratch_bytes,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,9 @@ SIGNATURES = {
     "spm_fill_outer": [_P, _D, _P, _P, _P],
     "spm_spmm": [_P, _P, _P, _I32, _P, _P],
     "spm_fst": [_P, _P, _I32, _P, _I32, _P],
+    "spm_contour_rule": [_D, _D, _I32, _P, _P],
+    "spm_contour_invsqrt_scratch": [_P, _I32, _P],
+    "spm_contour_invsqrt": [_P, _P, _D, _D, _I32, _I32, _P, _P, _P, ctypes.c_size_t, _P],
     "spm_ns_sqrt_scratch": [_P, _P],
     "spm_ns_sqrt": [_P, _P, _P, _P, _I32, _P, _P, ctypes.c_size_t, _P],
     "spm_expm_taylor_scratch": [_P, _P],

@@ -2212,3 +2212,46 @@ extern "C" int spm_newton_schulz(spm_pattern p, const double *A, double *X, int3
     if (!std::isfinite(last)) return fail(SPM_ENOTCONV, "spm_newton_schulz: residual is not finite");
     return SPM_OK;
 }
+
+
+extern "C" int spm_contour_invsqrt_scratch(spm_pattern p, int32_t ns_iters, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPM_EINVAL, "spm_contour_invsqrt_scratch: null pointer");
+    if (ns_iters < 0) return fail(SPM_EINVAL, "spm_contour_invsqrt_scratch: negative iteration count");
+    *bytes = 2 * (size_t)p->n_stored * sizeof(double) + ns_scratch(p, SPM_F64, 0) + (size_t)(ns_iters + 1) * sizeof(double);
+    return SPM_OK;
+}
+
+// A^{-1/2} by the contour quadrature of Section 4.4 (eq. ContInt): sum_k c_k X_k, X_k the
+// masked Newton-Schulz inverse of A + w_k^2 I started from 2 / (lam_min + lam_max + 2 w_k^2) I.
+extern "C" int spm_contour_invsqrt(spm_pattern p, const double *A, double lam_min, double lam_max, int32_t nodes,
+                                   int32_t ns_iters, double *out, double *residuals, void *scratch,
+                                   size_t scratch_bytes, void *stream)
+{
+    if (!p || !A || !out) return fail(SPM_EINVAL, "spm_contour_invsqrt: null pointer");
+    if (ns_iters < 0) return fail(SPM_EINVAL, "spm_contour_invsqrt: negative iteration count");
+    std::vector<double> w2(std::max(nodes, 1)), cw(std::max(nodes, 1));
+    int st;
+    if ((st = spm_contour_rule(lam_min, lam_max, nodes, w2.data(), cw.data()))) return st;
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), nsb = ns_scratch(p, SPM_F64, 0);
+    const size_t need = 2 * vb8 + nsb + (size_t)(ns_iters + 1) * sizeof(double);
+    if (!scratch || scratch_bytes < need) return fail(SPM_EINVAL, "spm_contour_invsqrt: scratch too small");
+    if (overlap(A, out, vb8) || overlap2(A, vb8, scratch, need) || overlap2(out, vb8, scratch, need))
+        return fail(SPM_EINVAL, "spm_contour_invsqrt: buffers overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ns = p->n_stored;
+    double *As = static_cast<double *>(scratch), *X = As + ns;
+    char *nsw = reinterpret_cast<char *>(X + ns);
+    double *res = reinterpret_cast<double *>(nsw + nsb);
+    hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)out);
+    for (int32_t k = 0; k < nodes; ++k) {
+        SPM_HIP(hipMemcpyAsync(As, A, vb8, hipMemcpyDeviceToDevice, s));
+        if ((st = spm::launch_axpy(p, SPM_F64, w2[k], nullptr, 1.0, As, s))) return st;          // A + w_k^2 I
+        const double alpha0 = 2.0 / (lam_min + lam_max + 2.0 * w2[k]);
+        if ((st = spm_newton_schulz(p, As, X, ns_iters, ns_iters, SPM_F64, alpha0, res, nullptr, nsw, nsb, s)))
+            return st;
+        if (residuals) SPM_HIP(hipMemcpyAsync(residuals + k, res + ns_iters, sizeof(double), hipMemcpyDeviceToDevice, s));
+        if ((st = spm::launch_axpy(p, SPM_F64, cw[k], X, 1.0, out, s))) return st;
+    }
+    return SPM_OK;
+}

@@ -900,3 +900,65 @@ extern "C" int spm_pattern_download_csr(spm_pattern p, int64_t *rp, int32_t *col
         }
     return SPM_OK;
 }
+
+// ---------------------------------------------------------------- contour quadrature rule
+namespace {
+
+// Jacobi elliptic functions sn, cn, dn of u for the parameter m (0 <= m < 1) by the
+// arithmetic-geometric mean (descending Landen transformation): with a_0 = 1,
+// b_0 = sqrt(1 - m), c_0 = sqrt(m) and a_{j+1} = (a_j + b_j)/2, b_{j+1} = sqrt(a_j b_j),
+// c_{j+1} = (a_j - b_j)/2 until c_N vanishes, phi_N = 2^N a_N u and
+// phi_{j-1} = (phi_j + asin(c_j sin(phi_j) / a_j)) / 2; then sn = sin phi_0,
+// cn = cos phi_0, dn = cos phi_0 / cos(phi_1 - phi_0).  The quarter period is
+// K(m) = pi / (2 a_N).
+struct Agm {
+    double a[40], c[40];
+    int n = 0;
+    explicit Agm(double m)
+    {
+        a[0] = 1.0;
+        c[0] = std::sqrt(m);
+        double b = std::sqrt(1.0 - m);
+        while (n < 38 && c[n] > 1e-17 * a[n]) {
+            a[n + 1] = 0.5 * (a[n] + b);
+            c[n + 1] = 0.5 * (a[n] - b);
+            b = std::sqrt(a[n] * b);
+            ++n;
+        }
+    }
+    double quarter_period() const { return 3.14159265358979323846 / (2.0 * a[n]); }
+    void sncndn(double u, double &sn, double &cn, double &dn) const
+    {
+        double phi = std::ldexp(a[n] * u, n), phi1 = phi;
+        for (int j = n; j >= 1; --j) {
+            phi1 = phi;
+            phi = 0.5 * (phi + std::asin(c[j] / a[j] * std::sin(phi)));
+        }
+        sn = std::sin(phi);
+        cn = std::cos(phi);
+        dn = n >= 1 ? cn / std::cos(phi1 - phi) : 1.0;
+    }
+};
+
+}  // namespace
+
+// Nodes and weights of A^{-1/2} ~ sum_k c_k (A + w_k^2 I)^{-1} for a spectrum in
+// [lam_min, lam_max] (Section 4.4, eq. ContInt): the midpoint rule in t for
+// A^{-1/2} = (2/pi) int_0^inf (A + w^2 I)^{-1} dw after w = sqrt(lam_min) sn(t)/cn(t),
+// parameter 1 - lam_min/lam_max, t over one quarter period.
+extern "C" int spm_contour_rule(double lam_min, double lam_max, int32_t nodes, double *w2, double *c)
+{
+    if (!w2 || !c) return fail(SPM_EINVAL, "spm_contour_rule: null pointer");
+    if (!(lam_min > 0.0) || !(lam_max >= lam_min) || !std::isfinite(lam_max) || nodes < 1)
+        return fail(SPM_EINVAL, "spm_contour_rule: need 0 < lam_min <= lam_max and nodes >= 1");
+    const Agm g(1.0 - lam_min / lam_max);
+    const double kq = g.quarter_period(), sm = std::sqrt(lam_min);
+    for (int k = 0; k < nodes; ++k) {
+        const double t = kq * (k + 0.5) / nodes;
+        double sn, cn, dn;
+        g.sncndn(t, sn, cn, dn);
+        w2[k] = lam_min * (sn / cn) * (sn / cn);
+        c[k] = 2.0 * kq * sm / (3.14159265358979323846 * nodes) * dn / (cn * cn);
+    }
+    return SPM_OK;
+}

@@ -217,6 +217,27 @@ def fill_outer(pat: Pattern, y, alpha=1.0, out=None) -> torch.Tensor:
     return out
 
 
+def contour_rule(lam_min: float, lam_max: float, nodes: int):
+    """Shifts w_k^2 and weights c_k of the contour quadrature for A^{-1/2} (host arrays)."""
+    w2 = np.empty(nodes, np.float64)
+    c = np.empty(nodes, np.float64)
+    call("spm_contour_rule", float(lam_min), float(lam_max), int(nodes), _ptr(w2), _ptr(c))
+    return w2, c
+
+
+def contour_invsqrt(pat: Pattern, A: torch.Tensor, lam_min: float, lam_max: float, nodes: int, ns_iters: int):
+    """A^{-1/2} on S by the contour quadrature with masked Newton-Schulz inverses;
+    returns (A^{-1/2}, final residual of each shifted inverse)."""
+    need = ctypes.c_size_t()
+    call("spm_contour_invsqrt_scratch", pat._h, int(ns_iters), ctypes.byref(need))
+    scratch = torch.empty((need.value + 7) // 8, dtype=torch.float64, device=A.device)
+    out = pat.empty("f64")
+    res = torch.zeros(max(nodes, 1), dtype=torch.float64, device=A.device)
+    call("spm_contour_invsqrt", pat._h, _ptr(A), float(lam_min), float(lam_max), int(nodes), int(ns_iters),
+         _ptr(out), _ptr(res), _ptr(scratch), scratch.numel() * 8, _stream())
+    return out, res[:nodes]
+
+
 def fst(tree: Tree, X: torch.Tensor, inverse: bool = False) -> torch.Tensor:
     """Fast samplet transform of the rows of X (shape (r, n)): T x (original point order ->
     basis order), or T^T x with inverse=True."""

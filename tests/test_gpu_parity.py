@@ -319,6 +319,26 @@ def test_ns_sqrt_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell):
     assert np.all(np.abs(r - np.array(res_ref)) <= 1e-12 * np.maximum(np.array(res_ref), 1e-3))
 
 
+@pytest.mark.parametrize("kind,n,leaf,q,eta,seed,p,ell,nodes,iters", [("cube2", 1024, 16, 1, 1.6, 1, 1, 0.5, 5, 16),
+                                                                      ("cube3", 1500, 32, 1, 1.0, 3, 2, 0.2, 3, 12)])
+def test_contour_invsqrt_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell, nodes, iters):
+    # contour quadrature for A^{-1/2}, A = K^eta / lambda_max + 1e-2 I, spectrum in [1e-2, 1.01]
+    print(f"case: contour_invsqrt {kind} n={n} leaf={leaf} eta={eta} nodes={nodes} iters={iters}", flush=True)
+    pr = oracle_problem(kind, n, leaf, q, eta, seed, p, ell)
+    pat = S.Pattern.from_csr(n, pr["rp"], pr["col"], pr["basis"].cluster_start)
+    mask = pr["mask"]
+    k = np.where(mask, pr["ks"], 0.0)
+    a = k / np.linalg.eigvalsh(k)[-1] + 1e-2 * np.eye(n)
+    A = pat.values_from_csr(to_dev(a[mask]))
+    out, res = S.contour_invsqrt(pat, A, 1e-2, 1.01, nodes, iters)
+    ref = ops.contour_invsqrt(a, mask, 1e-2, 1.01, nodes, iters)
+    err = relerr(pat.values_to_csr(out).cpu().numpy(), ref[mask])
+    r = res.cpu().numpy()
+    print(f"contour_invsqrt: error vs oracle {err:.3e}, node residuals {r}")
+    assert err < TOL64
+    assert np.all(np.isfinite(r)) and r.shape == (nodes,)
+
+
 def test_spmm_vs_oracle(S, cfg1):
     # S-matrix times a dense block of 10 columns (uniform entries, as in the paper's e_F)
     print("case: spmm cfg1 r=10", flush=True)

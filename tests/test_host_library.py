@@ -124,3 +124,25 @@ def test_tree_rejects_too_many_functions(lib):
     with pytest.raises(SpmError) as e:
         Tree(synth.points_cube(512, 2, 1), 64, 1)       # leaves of 64 points own 61 samplets
     assert e.value.status == -6
+
+
+@pytest.mark.parametrize("lo,hi,nodes,rtol", [(1e-2, 1.01, 7, 1e-12), (1e-4, 1.0, 12, 1e-12), (0.5, 2.0, 3, 1e-12),
+                                              (1.0, 1.0, 4, 1e-12), (1e-8, 10.0, 20, 2e-11)])
+def test_contour_rule_matches_oracle(lib, lo, hi, nodes, rtol):
+    """Host-side shifts and weights of the contour quadrature (Section 4.4) against the
+    oracle's rule, which evaluates the Jacobi functions with scipy.  At a spectral ratio
+    of 1e-9 the parameter sits 1e-9 below 1, where the two evaluations (descending
+    Landen here, scipy's own there) part by a few 1e-12."""
+    from oracle import ops
+    from paper_2211_11681_amd import spm
+    w2, c = spm.contour_rule(lo, hi, nodes)
+    ow2, oc = ops.contour_invsqrt_rule(lo, hi, nodes)
+    np.testing.assert_allclose(w2, ow2, rtol=rtol, atol=0)
+    np.testing.assert_allclose(c, oc, rtol=rtol, atol=0)
+
+
+def test_contour_rule_errors(lib):
+    w = np.empty(4)
+    for lo, hi, k in [(0.0, 1.0, 4), (2.0, 1.0, 4), (1.0, 2.0, 0), (float("nan"), 1.0, 4), (1.0, float("inf"), 4)]:
+        st = lib.spm_contour_rule(lo, hi, k, w.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p))
+        assert st == -1, (lo, hi, k)   # SPM_EINVAL
