@@ -211,9 +211,10 @@ int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_t inverse, 
 /* Y = A X: an S-matrix A (device F64 value array) times a dense block X of r
  * columns, the product of the paper's error estimator e_F(A) = ||A X||_F / ||X||_F
  * (Section 5.1).  X and Y: device F64, column-major n x r (column j at offset
- * j n), rows in basis order; Y must not overlap A or X.  Block row nu of Y sums the
- * tiles of block row nu in storage order (deterministic).  r = 0 does nothing.
- * Asynchronous on the stream; EINVAL on null or overlapping buffers or r < 0. */
+ * j n), rows in basis order; Y must not overlap A or X.  Each block row of Y is
+ * summed by one workgroup in a fixed order (deterministic run to run); X is read
+ * in passes of 16 columns.  r = 0 does nothing.  Asynchronous on the stream;
+ * EINVAL on null or overlapping buffers, r < 0, or n >= 2^25 (32-bit offsets). */
 int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double *Y, void *stream);
 
 /* Coupled Newton-Schulz iteration for the square root and the inverse square root

@@ -49,6 +49,10 @@ int upload_pattern_device(spm_pattern_s *p, hipStream_t s)
     if ((st = to_device(p->d_colprefix, p->colprefix, s))) return st;
     if ((st = to_device(p->d_rowbase, p->rowbase, s))) return st;
     if ((st = to_device(p->d_rowlen, p->rowlen, s))) return st;
+    if ((st = to_device(p->d_pc_rp, p->pc_rp, s))) return st;
+    if ((st = to_device(p->d_pc_off, p->pc_off, s))) return st;
+    if ((st = to_device(p->d_pc_g, p->pc_g, s))) return st;
+    if ((st = to_device(p->d_pc_w, p->pc_w, s))) return st;
     if ((st = to_device(p->d_nfun, p->nfun, s))) return st;
     if ((st = to_device(p->d_tile_row, p->tile_row, s))) return st;
     if ((st = to_device(p->d_tile_col, p->tile_col, s))) return st;
@@ -90,6 +94,7 @@ void free_pattern_device(spm_pattern_s *p)
 {
     release(p->d_cstart); release(p->d_blk_rp); release(p->d_tile_off); release(p->d_colprefix);
     release(p->d_rowbase); release(p->d_rowlen); release(p->d_csr_pos);
+    release(p->d_pc_rp); release(p->d_pc_off); release(p->d_pc_g); release(p->d_pc_w);
     release(p->d_nfun); release(p->d_tile_row); release(p->d_tile_col); release(p->d_trans);
     release(p->d_diag_tile); release(p->d_order); release(p->d_keep); release(p->d_partial);
     release(p->d_grp_mem); release(p->d_grp_s); release(p->d_grp_g); release(p->d_grp_R); release(p->d_gl_rp);
@@ -1547,30 +1552,181 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
 
 // Y = A X for an S-matrix A (tile layout) and a dense block X of r columns (column-major,
 // leading dimension n, basis order), the product behind the paper's error estimator
-// e_F (Section 5.1): block row nu of Y is the sum over the tiles of block row nu of
-// A_{nu mu} X_mu.  One workgroup per cluster; each thread owns outputs (row, column) of
-// the block row and adds the tiles in storage order (a fixed order).
-__global__ __launch_bounds__(128) void k_spmm(int32_t nc, int64_t n, int32_t r, const int64_t *__restrict__ blk_rp,
-                                              const int32_t *__restrict__ tile_col,
-                                              const int64_t *__restrict__ tile_off, const int32_t *__restrict__ nfun,
-                                              const int64_t *__restrict__ cstart, const double *__restrict__ A,
-                                              const double *__restrict__ X, double *__restrict__ Y)
+// e_F (Section 5.1).  The tiles of block row nu are stored one after the other, so the
+// row is a dense column-major panel of n_nu <= 32 rows; runs of tiles whose column
+// clusters follow on in the basis cover contiguous basis columns, and the host cuts
+// them into pieces of whole 16-column chunks.  One workgroup of kSpmmWaves waves per
+// block row, the waves taking the pieces in turn; their partial sums are added in LDS
+// in a fixed order.  Each piece is a small dense product (n_nu x w)(w x r):
+//  - n_nu > 8: v_mfma_f64_16x16x4f64.  Per 16 columns, lane l loads A at row
+//    16 rb + l%16 and X at column cc0 + 16 cb + l%16, both at piece columns
+//    l/16 + 4s (s = 0..3), so every value of A and X is loaded once.
+//  - n_nu <= 8 (where a 16-row MFMA would be mostly padding): plain FMAs.  Lane l takes
+//    piece column l%16 of each chunk and X columns l/16 + 4m; it loads its column of A
+//    once and keeps n_nu x 4 CB sums, folded over the 16 column lanes at the end.
+constexpr int kSpmmWaves = 8;
+
+// load at a uniform base plus a 32-bit byte offset (one VGPR per address)
+__device__ __forceinline__ double ld_off(const double *base, uint32_t byte_off)
 {
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <int NRB, int CB>
+__device__ __forceinline__ void spmm_mfma(int64_t q, int64_t p1, int nr, int64_t n, int r, int cc0,
+                                          const int64_t *__restrict__ pc_off, const int64_t *__restrict__ pc_g,
+                                          const int32_t *__restrict__ pc_w, const double *__restrict__ A,
+                                          const double *__restrict__ X, double (*red)[16 * CB + 1])
+{
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    dbl4 d[NRB][CB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) d[rb][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (; q < p1; q += kSpmmWaves) {
+        const int w = pc_w[q];
+        const double *aq = A + pc_off[q];
+        const int64_t g = pc_g[q];
+        const double *xr[CB];   // uniform: column cc0 + 16 cb of X at the piece's first basis column
+        bool xon[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            xon[cb] = cc0 + 16 * cb + lr < r;
+            xr[cb] = X + (int64_t)(cc0 + 16 * cb) * n + g;
+        }
+        const uint32_t xl = 8u * (uint32_t)(lr * n);
+        // U chunks of 16 columns per step, all of their loads in flight together
+        constexpr int U = NRB == 1 ? 4 : 2;
+        for (int j0 = 0; j0 < w; j0 += 16 * U) {
+            double av[U][NRB][4], xv[U][CB][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int sl = 0; sl < 4; ++sl) {
+                    const int jc = j0 + 16 * u + lk + 4 * sl;
+                    const bool jon = jc < w;
+#pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb) {
+                        const int row = 16 * rb + lr;
+                        av[u][rb][sl] = (jon && row < nr) ? ld_off(aq, 8u * (uint32_t)(jc * nr + row)) : 0.0;
+                    }
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        xv[u][cb][sl] = (jon && xon[cb]) ? ld_off(xr[cb], xl + 8u * (uint32_t)jc) : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            d[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][rb][sl], xv[u][cb][sl], d[rb][cb],
+                                                                             0, 0, 0);
+        }
+    }
+    // accumulator register k of lane l: row 16 rb + 4 k + l/16, column 16 cb + l%16
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[16 * rb + 4 * k + lk][16 * cb + lr] = d[rb][cb][k];
+}
+
+template <int MAXR, int CB>
+__device__ __forceinline__ void spmm_thin(int64_t q, int64_t p1, int nr, int64_t n, int r, int cc0,
+                                          const int64_t *__restrict__ pc_off, const int64_t *__restrict__ pc_g,
+                                          const int32_t *__restrict__ pc_w, const double *__restrict__ A,
+                                          const double *__restrict__ X, double (*red)[16 * CB + 1])
+{
+    constexpr int M = 4 * CB;
+    const int lane = threadIdx.x & 63, jl = lane & 15, cl = lane >> 4;
+    double acc[MAXR][M];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i)
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[i][m] = 0.0;
+    for (; q < p1; q += kSpmmWaves) {
+        const int w = pc_w[q];
+        const double *aq = A + pc_off[q];
+        const int64_t g = pc_g[q];
+        const double *xr[M];    // uniform: column cc0 + 4 m of X at the piece's first basis column
+        bool xon[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            xon[m] = cc0 + cl + 4 * m < r;
+            xr[m] = X + (int64_t)(cc0 + 4 * m) * n + g;
+        }
+        const uint32_t xl = 8u * (uint32_t)(cl * n);
+        constexpr int U = MAXR <= 4 ? 4 : 2;
+        for (int j0 = 0; j0 < w; j0 += 16 * U) {
+            double a[U][MAXR], x[U][M];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jc = j0 + 16 * u + jl;
+                const bool jon = jc < w;
+#pragma unroll
+                for (int i = 0; i < MAXR; ++i)
+                    a[u][i] = (jon && i < nr) ? ld_off(aq, 8u * (uint32_t)(jc * nr + i)) : 0.0;
+#pragma unroll
+                for (int m = 0; m < M; ++m) x[u][m] = (jon && xon[m]) ? ld_off(xr[m], xl + 8u * (uint32_t)jc) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < MAXR; ++i)
+#pragma unroll
+                    for (int m = 0; m < M; ++m) acc[i][m] = fma(a[u][i], x[u][m], acc[i][m]);
+        }
+    }
+    // fold the 16 column lanes of each X-column group (a fixed butterfly)
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            double v = acc[i][m];
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+            if (jl == 0 && i < nr) red[i][cl + 4 * m] = v;
+        }
+}
+
+template <int CB>
+__global__ __launch_bounds__(64 * kSpmmWaves) void k_spmm(int32_t nc, int64_t n, int32_t r,
+                                                          const int64_t *__restrict__ pc_rp,
+                                                          const int64_t *__restrict__ pc_off,
+                                                          const int64_t *__restrict__ pc_g,
+                                                          const int32_t *__restrict__ pc_w,
+                                                          const int32_t *__restrict__ nfun,
+                                                          const int64_t *__restrict__ cstart,
+                                                          const double *__restrict__ A, const double *__restrict__ X,
+                                                          double *__restrict__ Y)
+{
+    __shared__ double red[kSpmmWaves][32][16 * CB + 1];
     const int c = blockIdx.x;
     if (c >= nc) return;
     const int nr = nfun[c];
-    const int64_t row0 = cstart[c];
-    for (int o = threadIdx.x; o < nr * r; o += blockDim.x) {
-        const int i = o % nr, col = o / nr;
-        const double *xc = X + (int64_t)col * n;
-        double acc = 0.0;
-        for (int64_t t = blk_rp[c]; t < blk_rp[c + 1]; ++t) {
-            const int mu = tile_col[t], nm = nfun[mu];
-            const double *a = A + tile_off[t] + i;
-            const double *x = xc + cstart[mu];
-            for (int k = 0; k < nm; ++k) acc = fma(a[(int64_t)k * nr], x[k], acc);
+    if (nr == 0) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q0 = pc_rp[c] + wave, p1 = pc_rp[c + 1];
+    for (int cc0 = 0; cc0 < r; cc0 += 16 * CB) {
+        if (nr <= 4) spmm_thin<4, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        else if (nr <= 8) spmm_thin<8, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        else if (nr <= 16) spmm_mfma<1, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        else spmm_mfma<2, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        __syncthreads();
+        const int rc = min(16 * CB, r - cc0);
+        for (int o = threadIdx.x; o < nr * rc; o += blockDim.x) {
+            const int ii = o % nr, cc = o / nr;
+            double v = red[0][ii][cc];
+#pragma unroll
+            for (int w = 1; w < kSpmmWaves; ++w) v += red[w][ii][cc];
+            Y[(int64_t)(cc0 + cc) * n + cstart[c] + ii] = v;
         }
-        Y[(int64_t)col * n + row0 + i] = acc;
+        __syncthreads();
     }
 }
 
@@ -2088,11 +2244,14 @@ extern "C" int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t
     if (!p || !A || !X || !Y) return fail(SPM_EINVAL, "spm_spmm: null pointer");
     if (r < 0) return fail(SPM_EINVAL, "spm_spmm: negative column count");
     if (r == 0 || p->nc == 0) return SPM_OK;
+    if (p->n >= (int64_t(1) << 25)) return fail(SPM_EINVAL, "spm_spmm: n must be below 2^25");
     const size_t vb8 = (size_t)p->n_stored * sizeof(double), pb = (size_t)p->n * r * sizeof(double);
     if (overlap2(X, pb, Y, pb) || overlap2(A, vb8, Y, pb)) return fail(SPM_EINVAL, "spm_spmm: buffers overlap");
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_spmm, dim3((unsigned)p->nc), dim3(128), 0, s, p->nc, (int64_t)p->n, r, p->d_blk_rp.ptr,
-                       p->d_tile_col.ptr, p->d_tile_off.ptr, p->d_nfun.ptr, p->d_cstart.ptr, A, X, Y);
+    const dim3 g((unsigned)p->nc), b(64 * kSpmmWaves);
+// passes of 16 columns of X
+    hipLaunchKernelGGL(k_spmm<1>, g, b, 0, s, p->nc, (int64_t)p->n, r, p->d_pc_rp.ptr, p->d_pc_off.ptr,
+                       p->d_pc_g.ptr, p->d_pc_w.ptr, p->d_nfun.ptr, p->d_cstart.ptr, A, X, Y);
     SPM_HIP(hipGetLastError());
     return SPM_OK;
 }

@@ -711,6 +711,33 @@ void build_layout(spm_pattern_s *p)
         base += len * p->nfun[r];
     }
     p->n_stored = p->tile_off[nt];
+    // pieces for the S x dense product
+    p->pc_rp.assign(nc + 1, 0);
+    p->pc_off.clear();
+    p->pc_g.clear();
+    p->pc_w.clear();
+    for (int r = 0; r < nc; ++r) {
+        const int nr = p->nfun[r];
+        // whole 16-column chunks of at most kPieceEntries entries (at least one chunk)
+        const int32_t wmax = nr > 0 ? std::max(16, spm::kPieceEntries / nr / 16 * 16) : 16;
+        for (int64_t t = p->blk_rp[r]; t < p->blk_rp[r + 1];) {
+            // extend the run while the next tile's columns follow on in the basis
+            int64_t e = t + 1;
+            while (e < p->blk_rp[r + 1] &&
+                   p->cstart[p->tile_col[e]] == p->cstart[p->tile_col[e - 1]] + p->nfun[p->tile_col[e - 1]])
+                ++e;
+            const int64_t g0 = p->cstart[p->tile_col[t]];
+            const int64_t w = p->cstart[p->tile_col[e - 1]] + p->nfun[p->tile_col[e - 1]] - g0;
+            if (nr > 0)
+                for (int64_t j = 0; j < w; j += wmax) {
+                    p->pc_off.push_back(p->tile_off[t] + j * nr);
+                    p->pc_g.push_back(g0 + j);
+                    p->pc_w.push_back((int32_t)std::min<int64_t>(wmax, w - j));
+                }
+            t = e;
+        }
+        p->pc_rp[r + 1] = (int64_t)p->pc_w.size();
+    }
     // exact multiply-adds of one product: merge of the two sorted block rows per tile
     std::vector<double> part(16, 0.0);
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));

@@ -12,6 +12,7 @@
 namespace spm {
 
 constexpr int kMaxFun = 32;   // largest number of basis functions per cluster the kernels take
+constexpr int kPieceEntries = 2048;   // largest piece of a block row in the S x dense product
 
 int fail(int status, const std::string &msg);   // records msg, returns status
 
@@ -64,6 +65,12 @@ struct spm_pattern_s {
     std::vector<int64_t> colprefix;   // n_tiles: entries of the tile row before this tile
     std::vector<int64_t> rowbase, rowlen;  // nc: CSR position of the block row's first entry, entries per row
     std::vector<int32_t> diag_tile;   // nc
+    // pieces of the block rows for the S x dense product: runs of tiles whose column
+    // clusters are consecutive (a dense panel over a contiguous range of basis columns),
+    // cut into pieces of whole 16-column chunks and at most kPieceEntries entries
+    std::vector<int64_t> pc_rp;       // nc + 1
+    std::vector<int64_t> pc_off, pc_g;   // element offset in the value array, first basis column
+    std::vector<int32_t> pc_w;        // columns
     std::vector<int32_t> order;       // tile processing order (schedule)
     // grouped schedule of the FP64 product: groups of up to 4 consecutive clusters of
     // one size, and units = pairs of groups holding at least one output tile
@@ -96,6 +103,8 @@ struct spm_pattern_s {
     std::vector<int64_t> csr_pos;     // n_stored: CSR position or -1
     // device copies
     spm::DevBuf<int64_t> d_cstart, d_blk_rp, d_tile_off, d_colprefix, d_rowbase, d_rowlen, d_csr_pos;
+    spm::DevBuf<int64_t> d_pc_rp, d_pc_off, d_pc_g;
+    spm::DevBuf<int32_t> d_pc_w;
     spm::DevBuf<int32_t> d_nfun, d_tile_row, d_tile_col, d_trans, d_diag_tile, d_order;
     spm::DevBuf<int32_t> d_grp_mem, d_grp_s, d_grp_g, d_grp_R, d_gl_mu, d_gl_tile, d_unit_gr, d_unit_gc, d_unit_out,
         d_unit_order;

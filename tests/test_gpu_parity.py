@@ -353,6 +353,23 @@ def test_spmm_vs_oracle(S, cfg1):
     assert err < TOL64
 
 
+@pytest.mark.parametrize("kind,n,leaf,q,eta,seed,p,ell,r", [("cube3", 3000, 32, 1, 1.0, 4, 2, 0.2, 17),
+                                                             ("cube2", 2048, 16, 1, 1.6, 1, 1, 0.5, 3),
+                                                             ("sphere", 2048, 32, 1, 1.0, 5, 1, 0.3, 1)])
+def test_spmm_patterns_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell, r):
+    # S x dense on ragged cluster sizes; r = 17 takes two passes of 16 columns
+    print(f"case: spmm {kind} n={n} leaf={leaf} eta={eta} r={r}", flush=True)
+    pr = oracle_problem(kind, n, leaf, q, eta, seed, p, ell)
+    pat = S.Pattern.from_csr(n, pr["rp"], pr["col"], pr["basis"].cluster_start)
+    a = np.where(pr["mask"], pr["ks"], 0.0)
+    A = pat.values_from_csr(to_dev(a[pr["mask"]]))
+    x = 2 * synth.uniform(79, np.arange(r * n)).reshape(r, n) - 1
+    Y = S.spmm(pat, A, to_dev(x))
+    err = relerr(Y.cpu().numpy(), ops.spmm(a, x.T).T)
+    print(f"spmm: relative Frobenius error vs oracle {err:.3e}")
+    assert err < TOL64
+
+
 def test_fst_vs_oracle(S):
     # fast samplet transform of 3 vectors (original point order -> basis order) and back
     print("case: fst cube3 n=3000 leaf 32 q 1", flush=True)
