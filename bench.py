@@ -51,14 +51,16 @@ def parse():
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
     ap.add_argument("--workload", default="product",
-                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour"],
+                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour", "product_2d"],
                     help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
                          "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
                          "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072); "
                          "expm: the truncated exponential series of K (10 terms) on the product workload; "
                          "ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it; "
                          "contour: (K + 1e-2 I)^{-1/2} on it by a 6-node contour quadrature with 12 masked "
-                         "Newton-Schulz iterations per shifted inverse")
+                         "Newton-Schulz iterations per shifted inverse; product_2d: one product P_S(K K) at "
+                         "N = 1048576 in the unit square (Matern-3/2, l = 0.1, q = 2, eta = 1.6) in FP64, F32ACC "
+                         "and F32SPLIT, with the split modes' errors against FP64")
     return ap.parse_args()
 
 
@@ -369,6 +371,63 @@ def contour_main(args):
     print(json.dumps(out), flush=True)
 
 
+PRODUCT_2D = dict(workload="samplet_masked_product_square2d", n=1048576, dim=2, kernel="matern_nu1.5",
+                  lengthscale=0.1, vanishing_moments_degree=2, leaf=32, eta=1.6, seed=3)
+
+
+def product_2d_main(args):
+    """One product P_S(K K) on a million points in the unit square, in FP64 and in the
+    two FP32 modes, with the relative Frobenius error of each mode against FP64."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    os.environ.setdefault("SPM_PROGRESS", "1")       # the O(N^2) construction reports its panels
+    w = dict(PRODUCT_2D)
+    n = args.n if args.n != WORKLOAD["n"] else w["n"]
+    w["n"] = n
+    print(f"[bench] product_2d: tree for n={n}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    pts = synth.points_cube(n, w["dim"], w["seed"])
+    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+    print(f"[bench] product_2d: pattern and schedule ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    pat = S.Pattern.from_tree(tree, w["eta"])
+    print(f"[bench] product_2d: {pat.n_tiles} tiles, {pat.nnz} entries ({time.perf_counter() - t0:.1f} s); "
+          f"compressing K", file=sys.stderr, flush=True)
+    K = S.kernel_compress(pat, tree, 1, w["lengthscale"], 1.0 / n)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] product_2d: setup {t_setup:.1f} s, {pat.macs:.3e} MACs per product", file=sys.stderr, flush=True)
+    C = pat.empty("f64")
+    S.masked_gemm(pat, K, K, out=C)                                   # warm-up
+    reps = max(1, min(args.steps, 3))
+    _, ms = _timed(lambda: [S.masked_gemm(pat, K, K, out=C) for _ in range(reps)])
+    ms /= reps
+    print(f"[bench] product_2d: FP64 {ms:.1f} ms", file=sys.stderr, flush=True)
+    ref_norm = S.sqdist(pat, C).item() ** 0.5
+    out = {"metric": "pattern entries/s of P_S(A*B) (FP64), with FP32 modes at stated relative error",
+           "value": pat.nnz / (ms * 1e-3), "unit": "entries/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs, setup_s=t_setup),
+           "product_ms": ms, "algorithmic_TFLOPs": 2.0 * pat.macs / (ms * 1e-3) / 1e12}
+    for prec in ("f32acc", "f32split"):
+        Ks = S.convert(pat, K, "f64", prec)
+        Cs = S.masked_gemm(pat, Ks, Ks, prec=prec)                    # warm-up (and the result)
+        (_,), ms_p = _timed(lambda: (S.masked_gemm(pat, Ks, Ks, prec=prec, out=Cs),))
+        del Ks
+        C64 = S.convert(pat, Cs, prec, "f64")
+        del Cs
+        err = S.sqdist(pat, C64, C).item() ** 0.5 / ref_norm
+        del C64
+        torch.cuda.synchronize()
+        out[prec] = {"product_ms": ms_p, "entries_per_s": pat.nnz / (ms_p * 1e-3), "speedup_vs_f64": ms / ms_p,
+                     "rel_frobenius_err_vs_f64": err}
+        print(f"[bench] product_2d: {prec} {ms_p:.1f} ms, rel err {err:.3e}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -395,6 +454,8 @@ def main():
         return ns_sqrt_main(args)
     if args.workload == "contour":
         return contour_main(args)
+    if args.workload == "product_2d":
+        return product_2d_main(args)
     n = args.n
     w = WORKLOAD
     print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "spm_internal.h"
@@ -246,15 +248,21 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
     std::vector<std::vector<int32_t>> bylevel(depth + 1);
     for (int c = 0; c < nc; ++c) bylevel[t->level[c]].push_back(c);
 
-    const double budget = 2.0 * 1024 * 1024 * 1024;   // bytes of one panel
-    int lp = 0;
-    while (lp < depth) {
-        int64_t mx = 0;
-        for (int c : bylevel[lp]) mx = std::max(mx, t->psize[c]);
-        for (int l = 0; l < lp; ++l)
-            for (int c : bylevel[l]) if (t->son0[c] < 0) mx = std::max(mx, t->psize[c]);
-        if ((double)mx * n * 8.0 <= budget) break;
-        ++lp;
+    // Panel level lp: the panel buffer holds the rows of the largest panel root, the
+    // upper buffer the scaling rows of all panel roots, both n doubles wide.  Take the
+    // level that needs the fewest rows in the two together, among the levels whose
+    // panel fits the budget (the deepest level always qualifies as a fallback).
+    const double budget = 16.0 * 1024 * 1024 * 1024;  // bytes of one panel
+    int lp = depth;
+    int64_t best = -1;
+    for (int l = 0; l <= depth; ++l) {
+        int64_t mx = 0, nup = 0;
+        for (int c : bylevel[l]) { mx = std::max(mx, t->psize[c]); if (c != 0) nup += t->nscal[c]; }
+        for (int k = 0; k < l; ++k)
+            for (int c : bylevel[k])
+                if (t->son0[c] < 0) { mx = std::max(mx, t->psize[c]); if (c != 0) nup += t->nscal[c]; }
+        if ((double)mx * n * 8.0 > budget) continue;
+        if (best < 0 || mx + nup < best) { best = mx + nup; lp = l; }
     }
     std::vector<int32_t> roots;                         // panel roots, in cluster order
     for (int c = 0; c < nc; ++c)
@@ -366,7 +374,17 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
         return SPM_OK;
     };
 
+    // progress on stderr (SPM_PROGRESS set): the construction is O(n^2) and runs for
+    // minutes at a million points
+    const bool progress = std::getenv("SPM_PROGRESS") != nullptr;
+    const size_t tick = std::max<size_t>(1, panels.size() / 10);
+    size_t done = 0;
     for (const Panel &P : panels) {
+        if (progress && done > 0 && done % tick == 0) {
+            SPM_HIP(hipStreamSynchronize(s));
+            std::fprintf(stderr, "[spm] kernel_compress: %zu of %zu panels\n", done, panels.size());
+        }
+        ++done;
         const int64_t p0 = t->pstart[P.root], rows = t->psize[P.root];
         const int64_t total = rows * n;
         hipLaunchKernelGGL(k_eval, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20)), dim3(256), 0, s,
