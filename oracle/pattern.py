@@ -35,20 +35,23 @@ def diameters(tree: ClusterTree) -> np.ndarray:
     return _norm_rows(tree.hi - tree.lo)
 
 
+def block_row(tree: ClusterTree, eta: float, c: int, diam: np.ndarray | None = None) -> np.ndarray:
+    """The sorted clusters nu' with (c, nu') kept: eq. (cutoff) against every cluster."""
+    if diam is None:
+        diam = diameters(tree)
+    gap = np.maximum(0.0, np.maximum(tree.lo - tree.hi[c], tree.lo[c] - tree.hi))
+    dist = _norm_rows(gap)
+    bound = eta * np.maximum(diam[c], diam)
+    return np.nonzero(dist < bound)[0].astype(np.int64)
+
+
 def block_pattern(tree: ClusterTree, eta: float) -> list[np.ndarray]:
     """For each cluster nu, the sorted array of clusters nu' with (nu, nu') kept.
 
     Brute force over all cluster pairs (the definition, no tree traversal).
     """
-    nc = tree.n_clusters
     diam = diameters(tree)
-    out = []
-    for c in range(nc):
-        gap = np.maximum(0.0, np.maximum(tree.lo - tree.hi[c], tree.lo[c] - tree.hi))
-        dist = _norm_rows(gap)
-        bound = eta * np.maximum(diam[c], diam)
-        out.append(np.nonzero(dist < bound)[0].astype(np.int64))
-    return out
+    return [block_row(tree, eta, c, diam) for c in range(tree.n_clusters)]
 
 
 def block_csr(blocks: list[np.ndarray]):
