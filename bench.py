@@ -54,7 +54,7 @@ def parse():
                     choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour", "product_2d"],
                     help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
                          "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
-                         "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 131072); "
+                         "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 524288); "
                          "expm: the truncated exponential series of K (10 terms) on the product workload; "
                          "ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it; "
                          "contour: (K + 1e-2 I)^{-1/2} on it by a 6-node contour quadrature with 12 masked "
@@ -143,7 +143,7 @@ def recorded_traffic():
 
 NS_WORKLOAD = dict(workload="newton_schulz_cube3", n=262144, dim=3, kernel="matern_nu2.5", lengthscale=0.2,
                    vanishing_moments_degree=1, leaf=32, eta=1.0, seed=4, mu=1e-2, iterations=20, final_f64=3)
-GP_WORKLOAD = dict(workload="gp_lengthscale_gradient_sphere", n=131072, kernel="matern_nu1.5", lengthscale=0.3,
+GP_WORKLOAD = dict(workload="gp_lengthscale_gradient_sphere", n=524288, kernel="matern_nu1.5", lengthscale=0.3,
                    vanishing_moments_degree=1, leaf=32, eta=1.0, seed=5, mu=1e-2, iterations=15, fd_step=1e-4)
 
 

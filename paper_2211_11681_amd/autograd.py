@@ -10,8 +10,9 @@ Adjoints used (one symmetric pattern S, so every adjoint lives on S):
   Newton-Schulz step k:    Y_k = P_S(A X_k),  Z_k = 2I - Y_k,  X_{k+1} = P_S(X_k Z_k)
   f = y^T X y:             X-bar = f-bar P_S(y y^T)
   K^eta(l):                l-bar = <K-bar, dK^eta/dl>_S
-The Newton-Schulz forward keeps X_0 .. X_K (one FP64 checkpoint per iteration)
-and the reverse sweep recomputes Y_k and Z_k from them.
+The Newton-Schulz forward keeps X_0 .. X_{K-1} (one FP64 checkpoint per
+iteration; the sweep never reads X_K) and the reverse sweep recomputes Y_k and
+Z_k from them.
 """
 from __future__ import annotations
 
@@ -62,7 +63,8 @@ class NewtonSchulz(torch.autograd.Function):
         X, res, ck = spm.newton_schulz(pat, A, iters, n_final_f64=iters, bulk="f64", alpha0=alpha0,
                                        checkpoints=True)
         ctx.pat = pat
-        ctx.ck = ck
+        ctx.ck = ck[:iters]          # X_K itself is returned as X; the sweep reads X_0 .. X_{K-1}
+        del ck
         ctx.save_for_backward(A)
         ctx.mark_non_differentiable(res)
         return X, res
@@ -73,7 +75,7 @@ class NewtonSchulz(torch.autograd.Function):
         pat, ck = ctx.pat, ctx.ck
         Abar = torch.zeros_like(A)
         xbar = Xbar.contiguous()
-        for k in range(len(ck) - 2, -1, -1):
+        for k in range(len(ck) - 1, -1, -1):
             Xk = ck[k]
             Zk = spm.masked_gemm(pat, A, Xk)                      # Y_k
             spm.axpy(pat, 2.0, None, -1.0, Zk)                    # Z_k = 2I - Y_k
@@ -125,8 +127,9 @@ def gp_quadform_and_grad(pat, tree, matern_p: int, ell: float, mu: float, y: tor
     Returns (f, df/dl, residuals of the forward iteration).
     """
     ell_t = torch.tensor(float(ell), dtype=torch.float64, requires_grad=True)
-    K = CompressedKernel.apply(ell_t, pat, tree, matern_p, scale)
-    A = AddIdentity.apply(pat, K, mu)
+    # K itself is not kept: A = K + mu I is the only consumer, and the backward of
+    # the compression recomputes dK^eta/dl
+    A = AddIdentity.apply(pat, CompressedKernel.apply(ell_t, pat, tree, matern_p, scale), mu)
     X, res = NewtonSchulz.apply(pat, A, iters, alpha0)
     f = QuadForm.apply(pat, X, y)
     f.backward()
