@@ -143,7 +143,12 @@ int spm_values_to_csr(spm_pattern p, const double *vals, double *csr_vals, void 
  * lengthscale ell (deriv = 1: its derivative in ell) at the tree's points.
  * The pattern must have been built on the same tree's cluster ranges.
  * Exact O(N^2) evaluation by a two-sided fast samplet transform in panels;
- * temporary device memory is allocated and freed inside.
+ * temporary device memory is allocated and freed inside: one panel of rows of
+ * at most 16 GB, plus the scaling rows of the panel roots kept for the levels
+ * above them, at the tree level where the two together are smallest (42 GB at
+ * N = 2^20 in 2D).  Synchronises the stream before returning.  With the
+ * environment variable SPM_PROGRESS set, reports every tenth of its panels on
+ * stderr.  ENOMEM when the temporaries cannot be allocated.
  * ---------------------------------------------------------------------- */
 int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t matern_p, double ell, double scale,
                         int32_t deriv, double *vals, void *stream);
