@@ -51,7 +51,8 @@ def parse():
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
     ap.add_argument("--workload", default="product",
-                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour", "product_2d"],
+                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour", "product_2d",
+                             "matfun_tables"],
                     help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
                          "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
                          "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 524288); "
@@ -60,7 +61,8 @@ def parse():
                          "contour: (K + 1e-2 I)^{-1/2} on it by a 6-node contour quadrature with 12 masked "
                          "Newton-Schulz iterations per shifted inverse; product_2d: one product P_S(K K) at "
                          "N = 1048576 in the unit square (Matern-3/2, l = 0.1, q = 2, eta = 1.6) in FP64, F32ACC "
-                         "and F32SPLIT, with the split modes' errors against FP64")
+                         "and F32SPLIT, with the split modes' errors against FP64; matfun_tables: the protocol of "
+                         "the paper's square-root and exponential tables on a synthetic surface cloud")
     return ap.parse_args()
 
 
@@ -428,6 +430,72 @@ def product_2d_main(args):
     print(json.dumps(out), flush=True)
 
 
+MATFUN = dict(workload="matfun_tables_sphere", sizes=[5000, 10000, 50000, 100000], radius=0.5,
+              kernel="matern_nu0.5", lengthscale=0.5, vanishing_moments_degree=2, leaf=32, eta=1.25, seed=21,
+              mu=1e-4, lam_min=1e-4, lam_max=1.0, nodes=7, ns_iterations=24, exp_terms=8, exp_reference_terms=30,
+              coupled_ns_iterations=30)
+
+
+def matfun_tables_main(args):
+    """The protocol of the paper's tables for the square root and the exponential
+    (Section 5.3), on a synthetic stand-in for the scanned head: points on a sphere
+    of radius 1/2 (a closed surface about one unit across), kernel exp(-2r)/N,
+    mu = 1e-4, spectral bounds [mu, 1], seven quadrature nodes; the exponential by
+    8 terms against 30 terms of the series applied to a uniform block X (N x 10).
+    Degree q = 2 (three vanishing moments): the paper's q = 3 gives the root 40
+    functions in 3D, more than a cluster may own here."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    os.environ.setdefault("SPM_PROGRESS", "1")       # the quadrature reports its nodes
+    w = dict(MATFUN)
+    rows = []
+    t_all = time.perf_counter()
+    for n in w["sizes"]:
+        pts = w["radius"] * synth.points_sphere(n, w["seed"])
+        tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
+        pat = S.Pattern.from_tree(tree, w["eta"])
+        K = S.kernel_compress(pat, tree, 0, w["lengthscale"], 1.0 / n)
+        A = K.clone()
+        S.axpy(pat, w["mu"], None, 1.0, A)
+        X = torch.from_numpy(synth.uniform(95, np.arange(10 * n)).reshape(10, n)).cuda()
+        nx = float(torch.linalg.norm(X))
+        # square root: A^{1/2} = P_S(A A^{-1/2}) with A^{-1/2} by the contour quadrature
+        (Z, res), ms_c = _timed(lambda: S.contour_invsqrt(pat, A, w["lam_min"], w["lam_max"], w["nodes"],
+                                                            w["ns_iterations"]))
+        Y = S.masked_gemm(pat, A, Z)
+        e_sqrt = float(torch.linalg.norm(S.spmm(pat, Y, S.spmm(pat, Y, X)) - S.spmm(pat, A, X))) / nx
+        del Z, Y
+        # the coupled Newton-Schulz square root on the same A
+        (Yc, Zc, rc), ms_ns = _timed(lambda: S.ns_sqrt(pat, A, w["coupled_ns_iterations"]))
+        e_ns = float(torch.linalg.norm(S.spmm(pat, Yc, S.spmm(pat, Yc, X)) - S.spmm(pat, A, X))) / nx
+        del Yc, Zc
+        # exponential: 8 terms in the S-format against 30 terms applied to X
+        E, ms_e = _timed(lambda: S.expm_taylor(pat, K, w["exp_terms"]))
+        ref, t = X.clone(), X
+        for j in range(1, w["exp_reference_terms"] + 1):
+            t = S.spmm(pat, K, t) / j
+            ref += t
+        e_exp = float(torch.linalg.norm(ref - S.spmm(pat, E, X))) / nx
+        del E
+        row = {"n": n, "nnz": pat.nnz, "e_F_sqrt_contour": e_sqrt, "ms_contour": ms_c,
+               "node_residuals_max": float(res.max()), "e_F_sqrt_coupled_ns": e_ns, "ms_coupled_ns": ms_ns,
+               "coupled_ns_final_residual": float(rc[-1]), "e_F_exp": e_exp, "ms_exp": ms_e}
+        rows.append(row)
+        print(f"[bench] matfun N={n}: e_F sqrt contour {e_sqrt:.3e} ({ms_c:.0f} ms), coupled NS {e_ns:.3e} "
+              f"({ms_ns:.0f} ms), exp {e_exp:.3e} ({ms_e:.0f} ms)", file=sys.stderr, flush=True)
+        del K, A, X, ref, t
+        torch.cuda.empty_cache()
+    out = {"metric": "errors e_F of the S-format square root (contour quadrature) and exponential, by N",
+           "value": rows[-1]["e_F_sqrt_contour"], "unit": "e_F", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic", "config": w, "rows": rows,
+           "total_s": time.perf_counter() - t_all}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -456,6 +524,8 @@ def main():
         return contour_main(args)
     if args.workload == "product_2d":
         return product_2d_main(args)
+    if args.workload == "matfun_tables":
+        return matfun_tables_main(args)
     n = args.n
     w = WORKLOAD
     print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)

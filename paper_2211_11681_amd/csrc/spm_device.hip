@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "spm_internal.h"
@@ -2402,6 +2404,7 @@ extern "C" int spm_contour_invsqrt(spm_pattern p, const double *A, double lam_mi
     double *As = static_cast<double *>(scratch), *X = As + ns;
     char *nsw = reinterpret_cast<char *>(X + ns);
     double *res = reinterpret_cast<double *>(nsw + nsb);
+    const bool progress = std::getenv("SPM_PROGRESS") != nullptr;   // one line per node on stderr
     hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)out);
     for (int32_t k = 0; k < nodes; ++k) {
         SPM_HIP(hipMemcpyAsync(As, A, vb8, hipMemcpyDeviceToDevice, s));
@@ -2411,6 +2414,7 @@ extern "C" int spm_contour_invsqrt(spm_pattern p, const double *A, double lam_mi
             return st;
         if (residuals) SPM_HIP(hipMemcpyAsync(residuals + k, res + ns_iters, sizeof(double), hipMemcpyDeviceToDevice, s));
         if ((st = spm::launch_axpy(p, SPM_F64, cw[k], X, 1.0, out, s))) return st;
+        if (progress) std::fprintf(stderr, "[spm] contour_invsqrt: node %d of %d done\n", k + 1, nodes);
     }
     return SPM_OK;
 }

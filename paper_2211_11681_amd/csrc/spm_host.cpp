@@ -421,9 +421,10 @@ void build_groups(spm_pattern_s *p)
     while (c < nc) {
         if (p->nfun[c] == 0) { ++c; continue; }
         const int s = ceil4(p->nfun[c]);
-        // small slots fill exactly one 16-row block (four of 4, two of 8), so their
-        // units have a single 16-row side and run on the register-direct kernel
-        const int gmax = s <= 8 ? 16 / s : std::max(1, std::min(4, 128 / s));
+        // slots of up to 16 functions fill one 16-row block (four of 4, two of 8, one
+        // of 12 or 16), so their units have a single 16-row side and run on the
+        // register-direct kernel
+        const int gmax = s <= 16 ? 16 / s : std::max(1, std::min(4, 128 / s));
         int k = 0;
         const int g = (int)p->grp_s.size();
         while (c < nc && k < gmax && ceil4(p->nfun[c]) == s && p->nfun[c] > 0) {
