@@ -271,7 +271,8 @@ int spm_contour_rule(double lam_min, double lam_max, int32_t nodes, double *w2, 
  * residuals: device array of `nodes` doubles (the final Newton-Schulz residual of
  * each shifted inverse), or NULL.  scratch: device workspace of at least
  * spm_contour_invsqrt_scratch() bytes.  Synchronises the stream once per node (as
- * spm_newton_schulz does); ENOTCONV when a shifted inverse's residual is not finite,
+ * spm_newton_schulz does); with the environment variable SPM_PROGRESS set, reports
+ * each node on stderr.  ENOTCONV when a shifted inverse's residual is not finite,
  * EINVAL on bad arguments. */
 int spm_contour_invsqrt_scratch(spm_pattern p, int32_t ns_iters, size_t *bytes);
 int spm_contour_invsqrt(spm_pattern p, const double *A, double lam_min, double lam_max, int32_t nodes,
