@@ -478,7 +478,7 @@ constexpr int kSP = 8;    // middle clusters per stage
 // or the row is padding.
 struct KTab {
     int64_t kofs[kKS][8];
-    int32_t ks;           // padded k rows of the stage
+    int32_t ks;           // k rows of the stage (its clusters packed without padding)
     int32_t act;          // bit q (row member q), 4 + q (column member q): the member has a
                           // tile in some middle cluster of the stage (grouped kernel only)
     int32_t pad[2];
@@ -535,7 +535,9 @@ __device__ inline void gather_panel(const KTab *T, int slot_base, const double *
     constexpr int D = WIDTH * 8;
     constexpr int LD = WIDTH == 16 ? 7 : 5;   // log2 D
     const int X = 1 << lx;
-    const int nins = (ks * X + D - 1) >> LD;
+    // whole k steps: the MFMAs read rows up to the next multiple of 4, and rows past the
+    // stage's last cluster have offset -1 in the record (zero words)
+    const int nins = (((ks + 3) & ~3) * X + D - 1) >> LD;
     // with 16-byte lanes D = 128 >= X always (rows are at most 128 wide)
     if (WIDTH == 16 || lx <= LD) {
         // D >= X: lane row x is fixed, k = ins * (D / X) + (dl >> lx)
@@ -669,14 +671,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_grp(GroupArgs g, const dou
         for (int q = 0; q < kSP; ++q) {
             nmv[q] = __shfl(t_nm, q * 8);
             kbv[q] = kacc;
-            kacc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
+            kacc += q < t_np ? nmv[q] : 0;
         }
         const int kk = lane & 31;
         const bool rows = lane < 32;
         int m = -1;
 #pragma unroll
         for (int q = 0; q < kSP; ++q)
-            if (q < t_np && kk >= kbv[q] && kk < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
+            if (q < t_np && kk >= kbv[q] && kk < kbv[q] + nmv[q]) m = q;
         const int mm = m < 0 ? 0 : m;
         int nmm = 0, kbm = 0;
 #pragma unroll
@@ -1004,14 +1006,14 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         for (int q = 0; q < kSP; ++q) {
             nmv[q] = __shfl(t_nm, q * 8);
             kbv[q] = kacc;
-            kacc += q < t_np ? (nmv[q] + 3) & ~3 : 0;
+            kacc += q < t_np ? nmv[q] : 0;
         }
         const int kk = lane & 31;
         const bool rows = lane < 32;
         int m = -1;
 #pragma unroll
         for (int q = 0; q < kSP; ++q)
-            if (q < t_np && kk >= kbv[q] && kk < kbv[q] + ((nmv[q] + 3) & ~3)) m = q;
+            if (q < t_np && kk >= kbv[q] && kk < kbv[q] + nmv[q]) m = q;
         const int mm = m < 0 ? 0 : m;
         int nmm = 0, kbm = 0;
 #pragma unroll
@@ -1040,7 +1042,7 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
             if (q < t_np) {
                 Bm |= 1ull << kb;
                 Lm |= ((1ull << nmq) - 1) << kb;
-                kb += (nmq + 3) & ~3;
+                kb += nmq;
             }
         }
         const int kk = lane & 31;

@@ -509,7 +509,7 @@ void build_groups(spm_pattern_s *p)
             else {
                 if (pa) { pa[np] = (int32_t)a; pb[np] = (int32_t)b; }
                 ++np;
-                k += ceil4(p->nfun[x]);
+                k += p->nfun[x];
                 ++a; ++b;
             }
         }
@@ -547,14 +547,15 @@ void build_groups(spm_pattern_s *p)
             if (t >= 0) p->gl_offd[e * 4 + k] = p->tile_off[t];
         }
     }
-    // stages: consecutive middle clusters of a unit packed while their padded sizes sum to at most 32
+    // stages: consecutive middle clusters of a unit packed while their sizes sum to at most
+    // 32 k rows (a cluster may start at any row; only the stage's last k step is padded)
     std::vector<int64_t> nst(nu, 0);
     auto pack = [&](int64_t u, int32_t *out) {
         int64_t ns = 0;
         int kacc = 0, np = 0;
         const int64_t f0 = p->pair_off[u], f1 = p->pair_off[u + 1];
         for (int64_t f = f0; f < f1; ++f) {
-            const int km = ceil4(p->gl_nm[p->pair_a[f]]);
+            const int km = p->gl_nm[p->pair_a[f]];
             if (np == 0 || kacc + km > 32 || np == 8) {
                 if (out) out[ns] = (int32_t)(f - f0);
                 ++ns;
