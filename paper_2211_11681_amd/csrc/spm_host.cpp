@@ -526,11 +526,43 @@ void build_groups(spm_pattern_s *p)
     for (int64_t u = 0; u < nu; ++u) p->pair_off[u + 1] = p->pair_off[u] + cnt[u];
     p->pair_a.resize(p->pair_off[nu]);
     p->pair_b.resize(p->pair_off[nu]);
+    // Order of a unit's middle clusters (the sum over mu may run in any order): largest
+    // first, each topped up from the small end while the 32 k rows and 8 clusters of a
+    // stage allow, so that a 28-function leaf shares its stage with a 4-function
+    // cluster instead of leaving 4 rows empty; the stages below follow this order.
+    auto reorder = [&](int32_t *pa, int32_t *pb, int64_t np, std::vector<int64_t> &ord, std::vector<int32_t> &tmp) {
+        if (np < 2) return;
+        auto size = [&](int64_t q) { return p->nfun[p->gl_mu[pa[q]]]; };
+        ord.resize(np);
+        for (int64_t q = 0; q < np; ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return size(x) > size(y); });
+        tmp.clear();
+        int64_t i = 0, j = np - 1;
+        while (i <= j) {
+            int kacc = size(ord[i]), n = 1;
+            tmp.push_back((int32_t)ord[i++]);
+            while (i <= j && n < 8 && kacc + size(ord[j]) <= 32) {
+                kacc += size(ord[j]);
+                ++n;
+                tmp.push_back((int32_t)ord[j--]);
+            }
+        }
+        std::vector<int32_t> na(np), nb(np);
+        for (int64_t q = 0; q < np; ++q) { na[q] = pa[tmp[q]]; nb[q] = pb[tmp[q]]; }
+        std::copy(na.begin(), na.end(), pa);
+        std::copy(nb.begin(), nb.end(), pb);
+    };
     {
         std::vector<std::thread> th;
         for (unsigned w = 0; w < nth; ++w)
             th.emplace_back([&, w]() {
-                for (int64_t u = w; u < nu; u += nth) merge(u, p->pair_a.data() + p->pair_off[u], p->pair_b.data() + p->pair_off[u]);
+                std::vector<int64_t> ord;
+                std::vector<int32_t> tmp;
+                for (int64_t u = w; u < nu; u += nth) {
+                    int32_t *pa = p->pair_a.data() + p->pair_off[u], *pb = p->pair_b.data() + p->pair_off[u];
+                    merge(u, pa, pb);
+                    reorder(pa, pb, cnt[u], ord, tmp);
+                }
             });
         for (auto &x : th) x.join();
     }
