@@ -530,6 +530,7 @@ void build_groups(spm_pattern_s *p)
     // first, each topped up from the small end while the 32 k rows and 8 clusters of a
     // stage allow, so that a 28-function leaf shares its stage with a 4-function
     // cluster instead of leaving 4 rows empty; the stages below follow this order.
+    // Units with two wide sides keep the cluster order.
     auto reorder = [&](int32_t *pa, int32_t *pb, int64_t np, std::vector<int64_t> &ord, std::vector<int32_t> &tmp) {
         if (np < 2) return;
         auto size = [&](int64_t q) { return p->nfun[p->gl_mu[pa[q]]]; };
@@ -561,7 +562,10 @@ void build_groups(spm_pattern_s *p)
                 for (int64_t u = w; u < nu; u += nth) {
                     int32_t *pa = p->pair_a.data() + p->pair_off[u], *pb = p->pair_b.data() + p->pair_off[u];
                     merge(u, pa, pb);
-                    reorder(pa, pb, cnt[u], ord, tmp);
+                    // only for the register-direct classes: the staged kernel skips 16 x 16
+                    // blocks per stage, which mixed stages would make rarer
+                    if (p->grp_R[p->unit_gr[u]] == 16 || p->grp_R[p->unit_gc[u]] == 16)
+                        reorder(pa, pb, cnt[u], ord, tmp);
                 }
             });
         for (auto &x : th) x.join();
