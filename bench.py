@@ -279,7 +279,9 @@ def expm_main(args):
     (approx,), ms_spmm = _timed(lambda: (S.spmm(pat, E, X),))
     e_f = float(torch.linalg.norm(ref - approx) / torch.linalg.norm(X))
     print(f"[bench] expm: e_F(exp(K) - E) = {e_f:.3e}", file=sys.stderr, flush=True)
-    # fast samplet transform of the 10 probe vectors and back (point order <-> basis order)
+    # fast samplet transform of the 10 probe vectors and back (point order <-> basis order);
+    # the first call on a tree uploads its transform tables, so it is not timed
+    S.fst(tree, X)
     (Wt,), ms_fst = _timed(lambda: (S.fst(tree, X),))
     (Xb,), ms_ifst = _timed(lambda: (S.fst(tree, Wt, inverse=True),))
     fst_rt = float(torch.linalg.norm(Xb - X) / torch.linalg.norm(X))

@@ -208,9 +208,11 @@ int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, vo
  * K^Sigma = T K T^T): inverse = 0 gives Y = T X with X in the points' original
  * order and Y in basis order; inverse = 1 gives Y = T^T X (T is orthogonal) with X
  * in basis order and Y in the original order.  X, Y: distinct device F64 arrays,
- * r x n row-major (vector j at offset j n).  Uses a temporary device buffer of r n
- * doubles and the tree's transform tables (uploaded per call) and synchronises the
- * stream before returning.  EINVAL on null or overlapping buffers or r < 0. */
+ * r x n row-major (vector j at offset j n).  Uses a stream-ordered temporary of
+ * r n doubles and the tree's transform tables, which the first call on a tree
+ * uploads (synchronously) and the tree keeps until spm_tree_destroy; later calls
+ * are asynchronous on the stream.  EINVAL on null or overlapping buffers or r < 0;
+ * ENOMEM when the tables or the temporary cannot be allocated. */
 int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_t inverse, void *stream);
 
 /* Y = A X: an S-matrix A (device F64 value array) times a dense block X of r

@@ -21,6 +21,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "spm_internal.h"
@@ -415,6 +417,51 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
     return SPM_OK;
 }
 
+// The tree's transform tables on the device, uploaded once (synchronous copies).
+static int tree_tables(spm_tree t, spm::TreeDevice **out)
+{
+    spm::TreeDevice &D = *t->dev;
+    std::lock_guard<std::mutex> lock(D.mu);
+    if (!D.ready) {
+        D.release();
+        const int nc = t->nc, depth = t->depth;
+        const int64_t n = t->n;
+        std::vector<int32_t> kb(nc);
+        for (int c = 0; c < nc; ++c) kb[c] = c == 0 ? 0 : t->nscal[c];
+        std::vector<int64_t> sob(n);                   // basis index -> slot of its coefficient
+        for (int c = 0; c < nc; ++c)
+            for (int k = kb[c]; k < t->nin[c]; ++k) sob[t->cstart[c] + (k - kb[c])] = t->slots[t->slotoff[c] + k];
+        std::vector<std::vector<int32_t>> bylevel(depth + 1);
+        for (int c = 0; c < nc; ++c) bylevel[t->level[c]].push_back(c);
+        std::vector<int32_t> clist;
+        D.lvl.assign(depth + 1, {0, 0});
+        for (int l = 0; l <= depth; ++l) {
+            D.lvl[l] = {(int64_t)clist.size(), (int64_t)bylevel[l].size()};
+            clist.insert(clist.end(), bylevel[l].begin(), bylevel[l].end());
+        }
+        auto put = [](auto *&dst, const auto &v) -> int {
+            using T = typename std::decay_t<decltype(v)>::value_type;
+            if (v.empty()) return SPM_OK;
+            if (hipMalloc((void **)&dst, v.size() * sizeof(T)) != hipSuccess) {
+                dst = nullptr;
+                return fail(SPM_ENOMEM, "spm_fst: device tables");
+            }
+            SPM_HIP(hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+            return SPM_OK;
+        };
+        int st;
+        if ((st = put(D.q, t->qmat)) || (st = put(D.nin, t->nin)) || (st = put(D.qoff, t->qoff)) ||
+            (st = put(D.sloff, t->slotoff)) || (st = put(D.slots, t->slots)) || (st = put(D.sob, sob)) ||
+            (st = put(D.perm, t->perm)) || (st = put(D.clist, clist))) {
+            D.release();
+            return st;
+        }
+        D.ready = true;
+    }
+    *out = &D;
+    return SPM_OK;
+}
+
 // Fast samplet transform of r vectors (Section 3.2): Y = T X with X in the points'
 // original order and Y in basis order, or the inverse X = T^T Y.  The two-scale
 // transform is applied level by level in place on a tree-ordered copy, as in the
@@ -434,48 +481,35 @@ extern "C" int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_
     for (int c = 0; c < nc; ++c)
         if (t->nin[c] > kMaxIn) return fail(SPM_EUNSUPPORTED, "spm_fst: more than 64 inputs in one cluster");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<int32_t> kb(nc);
-    for (int c = 0; c < nc; ++c) kb[c] = c == 0 ? 0 : t->nscal[c];
-    std::vector<int64_t> sob(n);                       // basis index -> slot of its coefficient
-    for (int c = 0; c < nc; ++c)
-        for (int k = kb[c]; k < t->nin[c]; ++k) sob[t->cstart[c] + (k - kb[c])] = t->slots[t->slotoff[c] + k];
-    std::vector<std::vector<int32_t>> bylevel(depth + 1);
-    for (int c = 0; c < nc; ++c) bylevel[t->level[c]].push_back(c);
-    std::vector<int32_t> clist;
-    std::vector<std::pair<int64_t, int64_t>> lvl(depth + 1);
-    for (int l = 0; l <= depth; ++l) {
-        lvl[l] = {(int64_t)clist.size(), (int64_t)bylevel[l].size()};
-        clist.insert(clist.end(), bylevel[l].begin(), bylevel[l].end());
-    }
-    Dev<double> dq, dW;
-    Dev<int32_t> dnin, dcl;
-    Dev<int64_t> dqoff, dsloff, dslots, dsob, dperm;
+    spm::TreeDevice *D;
     int st;
-    if ((st = up(dq, t->qmat, s)) || (st = up(dnin, t->nin, s)) || (st = up(dqoff, t->qoff, s)) ||
-        (st = up(dsloff, t->slotoff, s)) || (st = up(dslots, t->slots, s)) || (st = up(dsob, sob, s)) ||
-        (st = up(dperm, t->perm, s)) || (st = up(dcl, clist, s)))
-        return st;
-    if (hipMalloc(&dW.p, (size_t)total * sizeof(double)) != hipSuccess) { dW.p = nullptr; return fail(SPM_ENOMEM, "spm_fst: work buffer"); }
+    if ((st = tree_tables(t, &D))) return st;
+    double *W = nullptr;                               // tree-ordered work copy, stream-ordered
+    if (hipMallocAsync((void **)&W, (size_t)total * sizeof(double), s) != hipSuccess)
+        return fail(SPM_ENOMEM, "spm_fst: work buffer");
     const unsigned g1 = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
     auto level = [&](int l, bool tr) {
-        auto [o, cnt] = lvl[l];
+        auto [o, cnt] = D->lvl[l];
         if (cnt == 0) return;
         dim3 g((unsigned)cnt, (unsigned)((r + 63) / 64));
         if (tr)
-            hipLaunchKernelGGL(k_coltr_t, g, dim3(64), 0, s, dW.p, (int64_t)r, n, dcl.p + o, dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p);
+            hipLaunchKernelGGL(k_coltr_t, g, dim3(64), 0, s, W, (int64_t)r, n, D->clist + o, D->nin, D->qoff, D->q,
+                               D->sloff, D->slots);
         else
-            hipLaunchKernelGGL(k_coltr, g, dim3(64), 0, s, dW.p, (int64_t)r, n, dcl.p + o, dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p);
+            hipLaunchKernelGGL(k_coltr, g, dim3(64), 0, s, W, (int64_t)r, n, D->clist + o, D->nin, D->qoff, D->q,
+                               D->sloff, D->slots);
     };
     if (!inverse) {
-        hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, dperm.p, X, dW.p);   // tree order
+        hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, D->perm, X, W);   // tree order
         for (int l = depth; l >= 0; --l) level(l, false);
-        hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, dsob.p, dW.p, Y);    // basis order
+        hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, D->sob, W, Y);    // basis order
     } else {
-        hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, s, n, total, dsob.p, X, dW.p);
+        hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, s, n, total, D->sob, X, W);
         for (int l = 0; l <= depth; ++l) level(l, true);
-        hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, s, n, total, dperm.p, dW.p, Y);   // original order
+        hipLaunchKernelGGL(k_scatter_rows, dim3(g1), dim3(256), 0, s, n, total, D->perm, W, Y);   // original order
     }
-    SPM_HIP(hipGetLastError());
-    SPM_HIP(hipStreamSynchronize(s));                 // the tables and the work buffer are freed on return
+    const hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(W, s);
+    if (e != hipSuccess) return fail(SPM_EHIP, std::string("spm_fst: launch failed: ") + hipGetErrorString(e));
     return SPM_OK;
 }

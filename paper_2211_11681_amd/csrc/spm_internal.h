@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/spm.h"
@@ -30,6 +33,27 @@ struct DevBuf {
     size_t n = 0;
 };
 
+// Device copies of a tree's transform tables (two-scale matrices, input slots, level
+// lists), uploaded on the first fast samplet transform and freed with the tree.  The
+// tree is immutable, so the copies stay valid; the mutex guards the one upload.
+struct TreeDevice {
+    std::mutex mu;
+    bool ready = false;
+    double *q = nullptr;
+    int32_t *nin = nullptr, *clist = nullptr;
+    int64_t *qoff = nullptr, *sloff = nullptr, *slots = nullptr, *sob = nullptr, *perm = nullptr;
+    std::vector<std::pair<int64_t, int64_t>> lvl;   // per level: offset and count in clist
+    void release()
+    {
+        for (void *x : {(void *)q, (void *)nin, (void *)clist, (void *)qoff, (void *)sloff, (void *)slots,
+                        (void *)sob, (void *)perm})
+            if (x) (void)hipFree(x);
+        q = nullptr; nin = clist = nullptr; qoff = sloff = slots = sob = perm = nullptr;
+        ready = false;
+    }
+    ~TreeDevice() { release(); }
+};
+
 }  // namespace spm
 
 struct spm_tree_s {
@@ -48,6 +72,7 @@ struct spm_tree_s {
     std::vector<double> qmat;
     std::vector<int64_t> slotoff;     // offset of each cluster's input slot list
     std::vector<int64_t> slots;       // input slots (tree-order point positions)
+    std::unique_ptr<spm::TreeDevice> dev = std::make_unique<spm::TreeDevice>();
 };
 
 struct spm_pattern_s {
