@@ -526,27 +526,47 @@ void build_groups(spm_pattern_s *p)
     for (int64_t u = 0; u < nu; ++u) p->pair_off[u + 1] = p->pair_off[u] + cnt[u];
     p->pair_a.resize(p->pair_off[nu]);
     p->pair_b.resize(p->pair_off[nu]);
-    // Order of a unit's middle clusters (the sum over mu may run in any order): largest
-    // first, each topped up from the small end while the 32 k rows and 8 clusters of a
-    // stage allow, so that a 28-function leaf shares its stage with a 4-function
-    // cluster instead of leaving 4 rows empty; the stages below follow this order.
-    // Units with two wide sides keep the cluster order.
-    auto reorder = [&](int32_t *pa, int32_t *pb, int64_t np, std::vector<int64_t> &ord, std::vector<int32_t> &tmp) {
+    // Order of a unit's middle clusters (the sum over mu may run in any order), for the
+    // units with a single 16-row side.  The register-direct kernel gives each 16-column
+    // block of the wide side to one wave, which skips a stage when none of its members
+    // has a tile there, so the clusters are first grouped by the set of wide-side
+    // members with a tile (fewer stages in which a block has work).  Inside a group they
+    // go largest first, each stage topped up from the small end while its 32 k rows and
+    // 8 clusters allow (a 28-function leaf shares its stage with a 4-function cluster
+    // instead of leaving 4 rows empty).  Units with two wide sides keep the cluster
+    // order: the staged kernel skips 16 x 16 blocks per stage, which mixed stages make
+    // rarer.
+    struct Item { int32_t key, size; int64_t q; };
+    auto reorder = [&](int64_t u, int32_t *pa, int32_t *pb, int64_t np, std::vector<Item> &it,
+                       std::vector<int32_t> &tmp) {
         if (np < 2) return;
-        auto size = [&](int64_t q) { return p->nfun[p->gl_mu[pa[q]]]; };
-        ord.resize(np);
-        for (int64_t q = 0; q < np; ++q) ord[q] = q;
-        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return size(x) > size(y); });
+        const bool wide_c = p->grp_R[p->unit_gc[u]] > 16, wide_r = p->grp_R[p->unit_gr[u]] > 16;
+        it.resize(np);
+        for (int64_t q = 0; q < np; ++q) {
+            int32_t key = 0;
+            const int32_t *tl = wide_c ? &p->gl_tile[(int64_t)pb[q] * 4] : wide_r ? &p->gl_tile[(int64_t)pa[q] * 4] : nullptr;
+            if (tl)
+                for (int k = 0; k < 4; ++k) key |= (tl[k] >= 0 ? 1 : 0) << k;
+            it[q] = {key, p->nfun[p->gl_mu[pa[q]]], q};
+        }
+        std::stable_sort(it.begin(), it.end(), [](const Item &x, const Item &y) {
+            return x.key != y.key ? x.key < y.key : x.size > y.size;
+        });
         tmp.clear();
-        int64_t i = 0, j = np - 1;
-        while (i <= j) {
-            int kacc = size(ord[i]), n = 1;
-            tmp.push_back((int32_t)ord[i++]);
-            while (i <= j && n < 8 && kacc + size(ord[j]) <= 32) {
-                kacc += size(ord[j]);
-                ++n;
-                tmp.push_back((int32_t)ord[j--]);
+        for (int64_t g0 = 0; g0 < np;) {
+            int64_t g1 = g0;
+            while (g1 < np && it[g1].key == it[g0].key) ++g1;
+            int64_t i = g0, j = g1 - 1;
+            while (i <= j) {
+                int kacc = it[i].size, n = 1;
+                tmp.push_back((int32_t)it[i++].q);
+                while (i <= j && n < 8 && kacc + it[j].size <= 32) {
+                    kacc += it[j].size;
+                    ++n;
+                    tmp.push_back((int32_t)it[j--].q);
+                }
             }
+            g0 = g1;
         }
         std::vector<int32_t> na(np), nb(np);
         for (int64_t q = 0; q < np; ++q) { na[q] = pa[tmp[q]]; nb[q] = pb[tmp[q]]; }
@@ -557,15 +577,13 @@ void build_groups(spm_pattern_s *p)
         std::vector<std::thread> th;
         for (unsigned w = 0; w < nth; ++w)
             th.emplace_back([&, w]() {
-                std::vector<int64_t> ord;
+                std::vector<Item> it;
                 std::vector<int32_t> tmp;
                 for (int64_t u = w; u < nu; u += nth) {
                     int32_t *pa = p->pair_a.data() + p->pair_off[u], *pb = p->pair_b.data() + p->pair_off[u];
                     merge(u, pa, pb);
-                    // only for the register-direct classes: the staged kernel skips 16 x 16
-                    // blocks per stage, which mixed stages would make rarer
                     if (p->grp_R[p->unit_gr[u]] == 16 || p->grp_R[p->unit_gc[u]] == 16)
-                        reorder(pa, pb, cnt[u], ord, tmp);
+                        reorder(u, pa, pb, cnt[u], it, tmp);
                 }
             });
         for (auto &x : th) x.join();
