@@ -526,16 +526,14 @@ void build_groups(spm_pattern_s *p)
     for (int64_t u = 0; u < nu; ++u) p->pair_off[u + 1] = p->pair_off[u] + cnt[u];
     p->pair_a.resize(p->pair_off[nu]);
     p->pair_b.resize(p->pair_off[nu]);
-    // Order of a unit's middle clusters (the sum over mu may run in any order), for the
-    // units with a single 16-row side.  The register-direct kernel gives each 16-column
-    // block of the wide side to one wave, which skips a stage when none of its members
-    // has a tile there, so the clusters are first grouped by the set of wide-side
-    // members with a tile (fewer stages in which a block has work).  Inside a group they
-    // go largest first, each stage topped up from the small end while its 32 k rows and
-    // 8 clusters allow (a 28-function leaf shares its stage with a 4-function cluster
-    // instead of leaving 4 rows empty).  Units with two wide sides keep the cluster
-    // order: the staged kernel skips 16 x 16 blocks per stage, which mixed stages make
-    // rarer.
+    // Order of a unit's middle clusters (the sum over mu may run in any order).  Both
+    // kernels skip work per stage: the register-direct one a 16-column (or 16-row) block
+    // of the wide side none of whose members has a tile in the stage, the staged one a
+    // 16 x 16 block whose row or column members have none.  So the clusters are first
+    // grouped by the sets of wide-side members with a tile (fewer stages in which a
+    // block has work).  Inside a group they go largest first, each stage topped up from
+    // the small end while its 32 k rows and 8 clusters allow (a 28-function leaf shares
+    // its stage with a 4-function cluster instead of leaving 4 rows empty).
     struct Item { int32_t key, size; int64_t q; };
     auto reorder = [&](int64_t u, int32_t *pa, int32_t *pb, int64_t np, std::vector<Item> &it,
                        std::vector<int32_t> &tmp) {
@@ -543,10 +541,11 @@ void build_groups(spm_pattern_s *p)
         const bool wide_c = p->grp_R[p->unit_gc[u]] > 16, wide_r = p->grp_R[p->unit_gr[u]] > 16;
         it.resize(np);
         for (int64_t q = 0; q < np; ++q) {
-            int32_t key = 0;
-            const int32_t *tl = wide_c ? &p->gl_tile[(int64_t)pb[q] * 4] : wide_r ? &p->gl_tile[(int64_t)pa[q] * 4] : nullptr;
-            if (tl)
-                for (int k = 0; k < 4; ++k) key |= (tl[k] >= 0 ? 1 : 0) << k;
+            int32_t key = 0;   // row members with a tile in bits 4..7, column members in bits 0..3
+            for (int k = 0; k < 4; ++k) {
+                if (wide_r) key |= (p->gl_tile[(int64_t)pa[q] * 4 + k] >= 0 ? 1 : 0) << (4 + k);
+                if (wide_c) key |= (p->gl_tile[(int64_t)pb[q] * 4 + k] >= 0 ? 1 : 0) << k;
+            }
             it[q] = {key, p->nfun[p->gl_mu[pa[q]]], q};
         }
         std::stable_sort(it.begin(), it.end(), [](const Item &x, const Item &y) {
@@ -582,8 +581,7 @@ void build_groups(spm_pattern_s *p)
                 for (int64_t u = w; u < nu; u += nth) {
                     int32_t *pa = p->pair_a.data() + p->pair_off[u], *pb = p->pair_b.data() + p->pair_off[u];
                     merge(u, pa, pb);
-                    if (p->grp_R[p->unit_gr[u]] == 16 || p->grp_R[p->unit_gc[u]] == 16)
-                        reorder(u, pa, pb, cnt[u], it, tmp);
+                    reorder(u, pa, pb, cnt[u], it, tmp);
                 }
             });
         for (auto &x : th) x.join();
