@@ -1408,7 +1408,19 @@ __device__ inline void quad_transpose(float (&v)[4], int q)
     v[3] = b1 ? t3 : p1;
 }
 
-template <int WAVES, int MC, bool QUAD>
+// lane 2m + p holds v = {row 2m at k step p, row 2m+1 at k step p, row 2m at step p + 2,
+// row 2m+1 at step p + 2}; afterwards it holds row 2m + p at k steps 0, 1, 2, 3
+// (each lane sends its partner the row the partner owns, one exchange per load)
+__device__ inline void pair_exchange(float (&v)[4], int p)
+{
+    const float r0 = dpp_xor1(p ? v[0] : v[1]);
+    const float r1 = dpp_xor1(p ? v[2] : v[3]);
+    const float a0 = p ? r0 : v[0], a1 = p ? v[1] : r0;
+    const float a2 = p ? r1 : v[2], a3 = p ? v[3] : r1;
+    v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3;
+}
+
+template <int WAVES, int MC, int LW>
 __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const float *__restrict__ A,
                                                             const float *__restrict__ B, float *__restrict__ C)
 {
@@ -1466,10 +1478,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
     const float *const zero = reinterpret_cast<const float *>(g_zero_word);
     const int q = lr & 3;
     // Fragments of half h (k steps 4h .. 4h + 3) of the stage whose record is T, kept as
-    // loaded (QUAD: rows 4m .. 4m + 3 at k step 4h + q) and put in MFMA order (the quad
-    // transpose) only when the half is computed, so no load is waited for when issued.
+    // loaded (LW = 4: rows 4m .. 4m + 3 at k step 4h + q; LW = 2: rows 2m, 2m + 1 at k
+    // steps 4h + p and 4h + p + 2, p = l % 2) and put in MFMA order (the quad transpose,
+    // or one pair exchange per load) only when the half is computed, so no load is
+    // waited for when issued.  LW = 2 needs every cluster size even: a row pair then
+    // never straddles two clusters or the end of one, and its 8 bytes are aligned.
     auto load_half = [&](const KTab *T, int h, flt4 &fa, flt4 (&fb)[MC]) {
-        if constexpr (QUAD) {
+        if constexpr (LW == 2) {
+            const int pp = lr & 1;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int k = 4 * (4 * h + 2 * j + pp) + lk;
+                const int64_t oa = T->kofs[k][slota];
+                const float2 va = *reinterpret_cast<const float2 *>((oka && oa >= 0) ? A + oa + (ia - pp) : zero);
+                fa[2 * j] = va.x;
+                fa[2 * j + 1] = va.y;
+#pragma unroll
+                for (int c = 0; c < MC; ++c) {
+                    const int64_t ob = T->kofs[k][slotb[c]];
+                    const float2 vb =
+                        *reinterpret_cast<const float2 *>((okb[c] && ob >= 0) ? B + ob + (jb[c] - pp) : zero);
+                    fb[c][2 * j] = vb.x;
+                    fb[c][2 * j + 1] = vb.y;
+                }
+            }
+        } else if constexpr (LW == 4) {
             const int k = 4 * (4 * h + q) + lk;
             const int64_t oa = T->kofs[k][slota];
             fa = *reinterpret_cast<const flt4 *>((oka && oa >= 0) ? A + oa + (ia - q) : zero);
@@ -1499,11 +1532,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
     // rows at and past ks load zeros, so all k steps run unconditionally
     auto compute_half = [&](const flt4 &fa_raw, const flt4 (&fb_raw)[MC]) {
         float fa[4] = {fa_raw.x, fa_raw.y, fa_raw.z, fa_raw.w};
-        if constexpr (QUAD) quad_transpose(fa, q);
+        if constexpr (LW == 4) quad_transpose(fa, q);
+        if constexpr (LW == 2) pair_exchange(fa, lr & 1);
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
             float fb[4] = {fb_raw[c].x, fb_raw[c].y, fb_raw[c].z, fb_raw[c].w};
-            if constexpr (QUAD) quad_transpose(fb, q);
+            if constexpr (LW == 4) quad_transpose(fb, q);
+            if constexpr (LW == 2) pair_exchange(fb, lr & 1);
 #pragma unroll
             for (int t = 0; t < 4; ++t) a32[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[t], fb[t], a32[c], 0, 0, 0);
         }
@@ -1966,7 +2001,7 @@ int launch_gemm_f32acc(spm_pattern p, const float *A, int ta, const float *B, in
     g.nfun = p->d_nfun.ptr;
     g.lxa = g.lxb = 4;
     g.WR = g.WC = g.nsplit = 1;
-    const bool quad = p->all_mult4;
+    const int lw = p->all_mult4 ? 4 : p->all_even ? 2 : 1;   // bytes per lane load / 4
     const size_t ring = ring_bytes<2>();
     for (const auto &L : p->launches) {
         if (st) break;
@@ -1978,17 +2013,17 @@ int launch_gemm_f32acc(spm_pattern p, const float *A, int ta, const float *B, in
         const void *k;
         int threads = 512;
         if (L.rb * L.cb == 1) {
-            k = quad ? (const void *)k_mgemm_f32acc<2, 1, true> : (const void *)k_mgemm_f32acc<2, 1, false>;
+            k = lw == 4 ? (const void *)k_mgemm_f32acc<2, 1, 4> : lw == 2 ? (const void *)k_mgemm_f32acc<2, 1, 2> : (const void *)k_mgemm_f32acc<2, 1, 1>;
             threads = 128;
         } else if (L.rb == 1 || L.cb == 1) {
             // one block per consumer wave (block rows or block columns)
-            k = quad ? (const void *)k_mgemm_f32acc<8, 1, true> : (const void *)k_mgemm_f32acc<8, 1, false>;
+            k = lw == 4 ? (const void *)k_mgemm_f32acc<8, 1, 4> : lw == 2 ? (const void *)k_mgemm_f32acc<8, 1, 2> : (const void *)k_mgemm_f32acc<8, 1, 1>;
         } else if (L.cb <= 2) {
-            k = quad ? (const void *)k_mgemm_f32acc<8, 2, true> : (const void *)k_mgemm_f32acc<8, 2, false>;
+            k = lw == 4 ? (const void *)k_mgemm_f32acc<8, 2, 4> : lw == 2 ? (const void *)k_mgemm_f32acc<8, 2, 2> : (const void *)k_mgemm_f32acc<8, 2, 1>;
         } else if (L.cb <= 4) {
-            k = quad ? (const void *)k_mgemm_f32acc<8, 4, true> : (const void *)k_mgemm_f32acc<8, 4, false>;
+            k = lw == 4 ? (const void *)k_mgemm_f32acc<8, 4, 4> : lw == 2 ? (const void *)k_mgemm_f32acc<8, 4, 2> : (const void *)k_mgemm_f32acc<8, 4, 1>;
         } else {
-            k = quad ? (const void *)k_mgemm_f32acc<8, 7, true> : (const void *)k_mgemm_f32acc<8, 7, false>;
+            k = lw == 4 ? (const void *)k_mgemm_f32acc<8, 7, 4> : lw == 2 ? (const void *)k_mgemm_f32acc<8, 7, 2> : (const void *)k_mgemm_f32acc<8, 7, 1>;
         }
         // a unit of one block row (RB == 1) with several column blocks gives each wave one
         // block; with several block rows each wave takes a row of blocks
