@@ -69,14 +69,21 @@ __global__ void k_eval(double *__restrict__ W, const double *__restrict__ pts, i
     }
 }
 
+// The transforms below keep Q (m x m) and the inputs of their 64 lanes (m x 64) in
+// dynamic LDS sized by the largest cluster of the launch, mmax: (mmax^2 + 64 mmax)
+// doubles, 24 KB for clusters of 32 inputs rather than 64 KB for the limit of 64, so
+// that several one-wave workgroups share a CU.
+__host__ __device__ constexpr size_t tr_lds_bytes(int mmax) { return (size_t)(mmax * mmax + 64 * mmax) * sizeof(double); }
+
 // Column transform of one tree level: block (cluster list entry, 64 rows).
 __global__ __launch_bounds__(64) void k_coltr(double *__restrict__ W, int64_t rows, int64_t n,
                                               const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
                                               const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
-                                              const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots)
+                                              const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots,
+                                              int mmax)
 {
-    __shared__ double sQ[kMaxIn * kMaxIn];
-    __shared__ double sIn[kMaxIn * 64];
+    extern __shared__ double tr_smem[];
+    double *sQ = tr_smem, *sIn = tr_smem + mmax * mmax;
     const int c = clist[blockIdx.x];
     const int m = nin[c];
     const double *Q = qmat + qoff[c];
@@ -99,10 +106,11 @@ __global__ __launch_bounds__(64) void k_coltr(double *__restrict__ W, int64_t ro
 __global__ __launch_bounds__(64) void k_rowtr(double *__restrict__ R, int64_t n, int64_t base,
                                               const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
                                               const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
-                                              const int64_t *__restrict__ rloff, const int64_t *__restrict__ rlist)
+                                              const int64_t *__restrict__ rloff, const int64_t *__restrict__ rlist,
+                                              int mmax)
 {
-    __shared__ double sQ[kMaxIn * kMaxIn];
-    __shared__ double sIn[kMaxIn * 64];
+    extern __shared__ double tr_smem[];
+    double *sQ = tr_smem, *sIn = tr_smem + mmax * mmax;
     const int c = clist[blockIdx.x];
     const int m = nin[c];
     const double *Q = qmat + qoff[c];
@@ -125,10 +133,11 @@ __global__ __launch_bounds__(64) void k_rowtr(double *__restrict__ R, int64_t n,
 __global__ __launch_bounds__(64) void k_coltr_t(double *__restrict__ W, int64_t rows, int64_t n,
                                                 const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
                                                 const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
-                                                const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots)
+                                                const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots,
+                                                int mmax)
 {
-    __shared__ double sQ[kMaxIn * kMaxIn];
-    __shared__ double sOut[kMaxIn * 64];
+    extern __shared__ double tr_smem[];
+    double *sQ = tr_smem, *sOut = tr_smem + mmax * mmax;
     const int c = clist[blockIdx.x];
     const int m = nin[c];
     const double *Q = qmat + qoff[c];
@@ -356,12 +365,20 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
     if (hipMalloc(&dW.p, (size_t)maxrows * n * sizeof(double)) != hipSuccess) { dW.p = nullptr; return fail(SPM_ENOMEM, "spm_kernel_compress: panel buffer"); }
     if (nu > 0 && hipMalloc(&dU.p, (size_t)nu * n * sizeof(double)) != hipSuccess) { dU.p = nullptr; return fail(SPM_ENOMEM, "spm_kernel_compress: upper buffer"); }
 
+    // largest number of inputs in a range of the cluster list (sizes the transforms' LDS)
+    auto mmax_of = [&](int64_t o, int64_t cnt) {
+        int mx = 1;
+        for (int64_t i = o; i < o + cnt; ++i) mx = std::max(mx, t->nin[clist[i]]);
+        return mx;
+    };
     auto coltr = [&](int64_t rows) -> int {
         for (int l = depth; l >= 0; --l) {
             auto [o, cnt] = lvl_all[l];
             if (cnt == 0) continue;
             dim3 g((unsigned)cnt, (unsigned)((rows + 63) / 64));
-            hipLaunchKernelGGL(k_coltr, g, dim3(64), 0, s, dW.p, rows, n, dcl.p + o, dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p);
+            const int mx = mmax_of(o, cnt);
+            hipLaunchKernelGGL(k_coltr, g, dim3(64), tr_lds_bytes(mx), s, dW.p, rows, n, dcl.p + o, dnin.p, dqoff.p,
+                               dq.p, dsloff.p, dslots.p, mx);
         }
         SPM_HIP(hipGetLastError());
         return SPM_OK;
@@ -395,7 +412,9 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
         if ((st = coltr(rows))) return st;
         for (auto [o, cnt] : P.lv) {
             dim3 g((unsigned)cnt, (unsigned)((n + 63) / 64));
-            hipLaunchKernelGGL(k_rowtr, g, dim3(64), 0, s, dW.p, n, p0, dcl.p + o, dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p);
+            const int mx = mmax_of(o, cnt);
+            hipLaunchKernelGGL(k_rowtr, g, dim3(64), tr_lds_bytes(mx), s, dW.p, n, p0, dcl.p + o, dnin.p, dqoff.p, dq.p,
+                               dsloff.p, dslots.p, mx);
         }
         SPM_HIP(hipGetLastError());
         if ((st = extract(dW.p, p0, P.t0, P.nt, dsloff.p, dslots.p))) return st;
@@ -409,7 +428,9 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
     for (size_t i = 0; i < lvl_up.size(); ++i) {
         auto [o, cnt] = lvl_up[i];
         dim3 g((unsigned)cnt, (unsigned)((n + 63) / 64));
-        hipLaunchKernelGGL(k_rowtr, g, dim3(64), 0, s, dU.p, n, (int64_t)0, dcl.p + o, dnin.p, dqoff.p, dq.p, durloff.p, durows.p);
+        const int mx = mmax_of(o, cnt);
+        hipLaunchKernelGGL(k_rowtr, g, dim3(64), tr_lds_bytes(mx), s, dU.p, n, (int64_t)0, dcl.p + o, dnin.p, dqoff.p,
+                           dq.p, durloff.p, durows.p, mx);
         SPM_HIP(hipGetLastError());
         if ((st = extract(dU.p, 0, tl_up[i].first, tl_up[i].second, durloff.p, durows.p))) return st;
     }
@@ -435,9 +456,11 @@ static int tree_tables(spm_tree t, spm::TreeDevice **out)
         for (int c = 0; c < nc; ++c) bylevel[t->level[c]].push_back(c);
         std::vector<int32_t> clist;
         D.lvl.assign(depth + 1, {0, 0});
+        D.lvl_mmax.assign(depth + 1, 1);
         for (int l = 0; l <= depth; ++l) {
             D.lvl[l] = {(int64_t)clist.size(), (int64_t)bylevel[l].size()};
             clist.insert(clist.end(), bylevel[l].begin(), bylevel[l].end());
+            for (int c : bylevel[l]) D.lvl_mmax[l] = std::max(D.lvl_mmax[l], t->nin[c]);
         }
         auto put = [](auto *&dst, const auto &v) -> int {
             using T = typename std::decay_t<decltype(v)>::value_type;
@@ -492,12 +515,13 @@ extern "C" int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_
         auto [o, cnt] = D->lvl[l];
         if (cnt == 0) return;
         dim3 g((unsigned)cnt, (unsigned)((r + 63) / 64));
+        const int mx = D->lvl_mmax[l];
         if (tr)
-            hipLaunchKernelGGL(k_coltr_t, g, dim3(64), 0, s, W, (int64_t)r, n, D->clist + o, D->nin, D->qoff, D->q,
-                               D->sloff, D->slots);
+            hipLaunchKernelGGL(k_coltr_t, g, dim3(64), tr_lds_bytes(mx), s, W, (int64_t)r, n, D->clist + o, D->nin,
+                               D->qoff, D->q, D->sloff, D->slots, mx);
         else
-            hipLaunchKernelGGL(k_coltr, g, dim3(64), 0, s, W, (int64_t)r, n, D->clist + o, D->nin, D->qoff, D->q,
-                               D->sloff, D->slots);
+            hipLaunchKernelGGL(k_coltr, g, dim3(64), tr_lds_bytes(mx), s, W, (int64_t)r, n, D->clist + o, D->nin,
+                               D->qoff, D->q, D->sloff, D->slots, mx);
     };
     if (!inverse) {
         hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, D->perm, X, W);   // tree order

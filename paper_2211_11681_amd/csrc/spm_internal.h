@@ -43,6 +43,7 @@ struct TreeDevice {
     int32_t *nin = nullptr, *clist = nullptr;
     int64_t *qoff = nullptr, *sloff = nullptr, *slots = nullptr, *sob = nullptr, *perm = nullptr;
     std::vector<std::pair<int64_t, int64_t>> lvl;   // per level: offset and count in clist
+    std::vector<int> lvl_mmax;                        // per level: largest number of inputs
     void release()
     {
         for (void *x : {(void *)q, (void *)nin, (void *)clist, (void *)qoff, (void *)sloff, (void *)slots,
