@@ -69,36 +69,48 @@ __global__ void k_eval(double *__restrict__ W, const double *__restrict__ pts, i
     }
 }
 
-// The transforms below keep Q (m x m) and the inputs of their 64 lanes (m x 64) in
-// dynamic LDS sized by the largest cluster of the launch, mmax: (mmax^2 + 64 mmax)
-// doubles, 24 KB for clusters of 32 inputs rather than 64 KB for the limit of 64, so
-// that several one-wave workgroups share a CU.
+// The transforms below keep Q (m x m; the row transform also the inputs of its 64
+// lanes, m x 64) in dynamic LDS sized by the largest cluster of the launch, mmax, so
+// that several workgroups share a CU (a fixed size for the limit of 64 inputs allowed
+// two).
 __host__ __device__ constexpr size_t tr_lds_bytes(int mmax) { return (size_t)(mmax * mmax + 64 * mmax) * sizeof(double); }
 
-// Column transform of one tree level: block (cluster list entry, 64 rows).
-__global__ __launch_bounds__(64) void k_coltr(double *__restrict__ W, int64_t rows, int64_t n,
-                                              const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
-                                              const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
-                                              const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots,
-                                              int mmax)
+// Column transform of one tree level: block (cluster list entry, 64 rows), four waves
+// taking the rows in turn.  Lane k of a wave owns slot k of the cluster: one coalesced
+// load reads the row's inputs, lane k forms output k from all inputs (read out of the
+// lanes that hold them) and Q^T kept in LDS, and stores it back to slot k.
+__device__ __forceinline__ double lane_value(double v, int i)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+    return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(256) void k_coltr(double *__restrict__ W, int64_t rows, int64_t n,
+                                               const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
+                                               const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
+                                               const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots,
+                                               int mmax)
 {
     extern __shared__ double tr_smem[];
-    double *sQ = tr_smem, *sIn = tr_smem + mmax * mmax;
+    double *sQt = tr_smem;                           // sQt[i * m + k] = Q[k * m + i]
     const int c = clist[blockIdx.x];
     const int m = nin[c];
     const double *Q = qmat + qoff[c];
-    for (int e = threadIdx.x; e < m * m; e += 64) sQ[e] = Q[e];
-    const int64_t *sl = slots + slotoff[c];
-    const int64_t r = (int64_t)blockIdx.y * 64 + threadIdx.x;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) sQt[(e % m) * m + e / m] = Q[e];
     __syncthreads();
-    if (r >= rows) return;
-    double *row = W + r * n;
-    for (int i = 0; i < m; ++i) sIn[i * 64 + threadIdx.x] = row[sl[i]];
-    for (int k = 0; k < m; ++k) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t slot = lane < m ? slots[slotoff[c] + lane] : 0;
+    for (int rr = wave; rr < 64; rr += 4) {
+        const int64_t r = (int64_t)blockIdx.y * 64 + rr;
+        if (r >= rows) break;
+        double *row = W + r * n;
+        const double v = lane < m ? row[slot] : 0.0;
         double acc = 0.0;
-        for (int i = 0; i < m; ++i) acc = fma(sQ[k * m + i], sIn[i * 64 + threadIdx.x], acc);
-        row[sl[k]] = acc;
+        for (int i = 0; i < m; ++i) acc = fma(sQt[i * m + min(lane, m - 1)], lane_value(v, i), acc);
+        if (lane < m) row[slot] = acc;
     }
+    (void)mmax;
 }
 
 // Row transform: block (cluster list entry, 64 columns); the cluster's input rows
@@ -129,30 +141,33 @@ __global__ __launch_bounds__(64) void k_rowtr(double *__restrict__ R, int64_t n,
 
 // Inverse of the column transform for one tree level (levels run root first): the
 // cluster's outputs, read at its slots, are mapped back by Q (Q is orthogonal and the
-// forward step applies Q^T), writing input i to slot i.
-__global__ __launch_bounds__(64) void k_coltr_t(double *__restrict__ W, int64_t rows, int64_t n,
-                                                const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
-                                                const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
-                                                const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots,
-                                                int mmax)
+// forward step applies Q^T), writing input i to slot i.  Same layout as k_coltr: lane i
+// forms input i from all outputs and Q kept in LDS.
+__global__ __launch_bounds__(256) void k_coltr_t(double *__restrict__ W, int64_t rows, int64_t n,
+                                                 const int32_t *__restrict__ clist, const int32_t *__restrict__ nin,
+                                                 const int64_t *__restrict__ qoff, const double *__restrict__ qmat,
+                                                 const int64_t *__restrict__ slotoff, const int64_t *__restrict__ slots,
+                                                 int mmax)
 {
     extern __shared__ double tr_smem[];
-    double *sQ = tr_smem, *sOut = tr_smem + mmax * mmax;
+    double *sQ = tr_smem;                            // sQ[k * m + i] = Q[k * m + i]
     const int c = clist[blockIdx.x];
     const int m = nin[c];
     const double *Q = qmat + qoff[c];
-    for (int e = threadIdx.x; e < m * m; e += 64) sQ[e] = Q[e];
-    const int64_t *sl = slots + slotoff[c];
-    const int64_t r = (int64_t)blockIdx.y * 64 + threadIdx.x;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) sQ[e] = Q[e];
     __syncthreads();
-    if (r >= rows) return;
-    double *row = W + r * n;
-    for (int k = 0; k < m; ++k) sOut[k * 64 + threadIdx.x] = row[sl[k]];
-    for (int i = 0; i < m; ++i) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t slot = lane < m ? slots[slotoff[c] + lane] : 0;
+    for (int rr = wave; rr < 64; rr += 4) {
+        const int64_t r = (int64_t)blockIdx.y * 64 + rr;
+        if (r >= rows) break;
+        double *row = W + r * n;
+        const double v = lane < m ? row[slot] : 0.0;
         double acc = 0.0;
-        for (int k = 0; k < m; ++k) acc = fma(sQ[k * m + i], sOut[k * 64 + threadIdx.x], acc);
-        row[sl[i]] = acc;
+        for (int k = 0; k < m; ++k) acc = fma(sQ[k * m + min(lane, m - 1)], lane_value(v, k), acc);
+        if (lane < m) row[slot] = acc;
     }
+    (void)mmax;
 }
 
 // Row-wise permutations of an r x n block: gather out[j][k] = in[j][idx[k]], scatter
@@ -377,8 +392,8 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
             if (cnt == 0) continue;
             dim3 g((unsigned)cnt, (unsigned)((rows + 63) / 64));
             const int mx = mmax_of(o, cnt);
-            hipLaunchKernelGGL(k_coltr, g, dim3(64), tr_lds_bytes(mx), s, dW.p, rows, n, dcl.p + o, dnin.p, dqoff.p,
-                               dq.p, dsloff.p, dslots.p, mx);
+            hipLaunchKernelGGL(k_coltr, g, dim3(256), (size_t)mx * mx * sizeof(double), s, dW.p, rows, n, dcl.p + o,
+                               dnin.p, dqoff.p, dq.p, dsloff.p, dslots.p, mx);
         }
         SPM_HIP(hipGetLastError());
         return SPM_OK;
@@ -517,11 +532,11 @@ extern "C" int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_
         dim3 g((unsigned)cnt, (unsigned)((r + 63) / 64));
         const int mx = D->lvl_mmax[l];
         if (tr)
-            hipLaunchKernelGGL(k_coltr_t, g, dim3(64), tr_lds_bytes(mx), s, W, (int64_t)r, n, D->clist + o, D->nin,
-                               D->qoff, D->q, D->sloff, D->slots, mx);
+            hipLaunchKernelGGL(k_coltr_t, g, dim3(256), (size_t)mx * mx * sizeof(double), s, W, (int64_t)r, n,
+                               D->clist + o, D->nin, D->qoff, D->q, D->sloff, D->slots, mx);
         else
-            hipLaunchKernelGGL(k_coltr, g, dim3(64), tr_lds_bytes(mx), s, W, (int64_t)r, n, D->clist + o, D->nin,
-                               D->qoff, D->q, D->sloff, D->slots, mx);
+            hipLaunchKernelGGL(k_coltr, g, dim3(256), (size_t)mx * mx * sizeof(double), s, W, (int64_t)r, n,
+                               D->clist + o, D->nin, D->qoff, D->q, D->sloff, D->slots, mx);
     };
     if (!inverse) {
         hipLaunchKernelGGL(k_gather_rows, dim3(g1), dim3(256), 0, s, n, total, D->perm, X, W);   // tree order
