@@ -370,6 +370,26 @@ def test_spmm_patterns_vs_oracle(S, kind, n, leaf, q, eta, seed, p, ell, r):
     assert err < TOL64
 
 
+def test_matrix_function_argument_errors(S, cfg1):
+    # the drivers added for Section 4.4 reject bad arguments before any device work
+    from paper_2211_11681_amd._lib import SpmError
+    pat, n = cfg1["pat"], cfg1["n"]
+    A = pat.empty("f64").zero_()
+    S.axpy(pat, 1.0, None, 1.0, A)                                 # A = I
+    for lo, hi, nodes in [(0.0, 1.0, 3), (1.0, 0.5, 3), (0.5, 1.0, 0), (float("nan"), 1.0, 3)]:
+        with pytest.raises(SpmError):
+            S.contour_invsqrt(pat, A, lo, hi, nodes, 4)
+    with pytest.raises(SpmError):
+        S.contour_invsqrt(pat, A, 0.5, 2.0, 3, -1)
+    # a single node on the identity with bounds [1, 1] gives c_1 (1 + w_1^2)^{-1} I
+    Z, res = S.contour_invsqrt(pat, A, 1.0, 1.0, 1, 30)
+    w2, c = S.contour_rule(1.0, 1.0, 1)
+    z = pat.values_to_csr(Z).cpu().numpy()
+    d = np.eye(n)[cfg1["mask"]]
+    assert np.max(np.abs(z - c[0] / (1.0 + w2[0]) * d)) < 1e-14
+    assert float(res[0]) < 1e-15
+
+
 def test_fst_vs_oracle(S):
     # fast samplet transform of 3 vectors (original point order -> basis order) and back
     print("case: fst cube3 n=3000 leaf 32 q 1", flush=True)
