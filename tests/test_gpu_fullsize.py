@@ -11,6 +11,11 @@ Sampled entries of K^eta and of C are compared one by one.
 
 Tolerance per entry: 1e-12 * ||K_i|| ||K_j|| for C (the Cauchy-Schwarz scale of
 the sum) and 1e-12 * ||K_i|| for K.
+
+The same run checks the two operations that the error measure e_F uses, as the
+benchmark runs them at this size: rows of Y = K^eta X for a uniform block X of 10
+vectors against the oracle rows (tolerance 1e-12 * ||K_i|| ||X||), and the fast
+samplet transform of X against the oracle's sparse T at every entry (1e-12 * ||X||).
 """
 import numpy as np
 import pytest
@@ -100,3 +105,19 @@ def test_product_full_size_sampled_entries():
     kerr = np.abs(gk - np.array(kref)) / np.array(kscale)
     print(f"K: {len(kpos)} sampled entries, max error / |K_i| = {kerr.max():.3e}", flush=True)
     assert kerr.max() < 1e-12
+
+    # S x dense and the fast samplet transform at full size
+    from oracle import ops
+    x = synth.uniform(91, np.arange(10 * N)).reshape(10, N)
+    X = torch.from_numpy(x).cuda()
+    Y = spm.spmm(pat, K, X).cpu().numpy()
+    yref = keta @ x.T                                               # sampled rows, 10 columns
+    nx = np.linalg.norm(x)
+    yerr = np.abs(Y[:, rows].T - yref).max(axis=1) / (norms * nx)
+    print(f"S x dense: {len(rows)} sampled rows, max error / (|K_i||X|) = {yerr.max():.3e}", flush=True)
+    assert yerr.max() < 1e-12
+    W = spm.fst(t, X).cpu().numpy()
+    wref = ops.fst(ob, x.T).T
+    ferr = np.abs(W - wref).max() / nx
+    print(f"FST: all {W.size} entries, max error / |X| = {ferr:.3e}", flush=True)
+    assert ferr < 1e-12

@@ -127,7 +127,7 @@ def test_tree_rejects_too_many_functions(lib):
 
 
 @pytest.mark.parametrize("lo,hi,nodes,rtol", [(1e-2, 1.01, 7, 1e-12), (1e-4, 1.0, 12, 1e-12), (0.5, 2.0, 3, 1e-12),
-                                              (1.0, 1.0, 4, 1e-12), (1e-8, 10.0, 20, 2e-11)])
+                                              (1.0, 1.0, 4, 1e-12), (1e-8, 10.0, 20, 2e-11), (0.3, 0.3, 5, 1e-12)])
 def test_contour_rule_matches_oracle(lib, lo, hi, nodes, rtol):
     """Host-side shifts and weights of the contour quadrature (Section 4.4) against the
     oracle's rule, which evaluates the Jacobi functions with scipy.  At a spectral ratio
@@ -139,6 +139,8 @@ def test_contour_rule_matches_oracle(lib, lo, hi, nodes, rtol):
     ow2, oc = ops.contour_invsqrt_rule(lo, hi, nodes)
     np.testing.assert_allclose(w2, ow2, rtol=rtol, atol=0)
     np.testing.assert_allclose(c, oc, rtol=rtol, atol=0)
+    if lo == hi:   # parameter 0: the rule is exact at lam = lo (closed form)
+        assert np.sum(c / (lo + w2)) == pytest.approx(lo ** -0.5, rel=1e-14)
 
 
 def test_contour_rule_errors(lib):

@@ -361,3 +361,14 @@ def test_contour_invsqrt_full_pattern_is_library():
     x = ops.contour_invsqrt(a, np.ones((n, n), bool), 0.05, 1.5, 16, 40)
     ref = np.linalg.inv(scipy.linalg.sqrtm(a).real)
     assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("lam,nodes", [(0.3, 1), (2.0, 3), (1e-3, 7)])
+def test_contour_rule_exact_at_unit_ratio(lam, nodes):
+    # With lam_min = lam_max the parameter is 0, sn = sin, cn = cos, dn = 1 and the
+    # quarter period is pi/2: c_k / (lam + w_k^2) = 1 / (nodes sqrt(lam)) for every
+    # node, so the rule reproduces lam^{-1/2} exactly whatever the node count.
+    w2, c = ops.contour_invsqrt_rule(lam, lam, nodes)
+    assert np.sum(c / (lam + w2)) == pytest.approx(lam ** -0.5, rel=1e-14)
+    t = (np.pi / 2) * (np.arange(nodes) + 0.5) / nodes
+    np.testing.assert_allclose(w2, lam * np.tan(t) ** 2, rtol=1e-13)
