@@ -16,6 +16,12 @@ The same run checks the two operations that the error measure e_F uses, as the
 benchmark runs them at this size: rows of Y = K^eta X for a uniform block X of 10
 vectors against the oracle rows (tolerance 1e-12 * ||K_i|| ||X||), and the fast
 samplet transform of X against the oracle's sparse T at every entry (1e-12 * ||X||).
+
+It also certifies the masked Newton-Schulz inverse of A = K^eta + 1e-2 I (20 FP64
+iterations) at this size: for the sampled pairs (i, j) in S the residual entry
+delta_ij - sum_{k in S_i cap S_j} A_ik X_kj, with the oracle's rows of A and the
+library's X, must vanish to 1e-10 of sum_k |A_ik X_kj| (the converged iteration has
+P_S(A X) = I on S; a wrong iterate leaves residuals of order 1).
 """
 import numpy as np
 import pytest
@@ -121,3 +127,29 @@ def test_product_full_size_sampled_entries():
     ferr = np.abs(W - wref).max() / nx
     print(f"FST: all {W.size} entries, max error / |X| = {ferr:.3e}", flush=True)
     assert ferr < 1e-12
+
+    # masked Newton-Schulz inverse: sampled entries of I - P_S(A X)
+    mu = 1e-2
+    A = K.clone()
+    spm.axpy(pat, mu, None, 1.0, A)
+    Xns, res, _ = spm.newton_schulz(pat, A, 20, 20, "f64", 2.0 / (1.0 + 2.0 * mu))
+    arow = keta.copy()
+    arow[np.arange(len(rows)), rows] += mu
+    worst = 0.0
+    def positions(ii, j):                                          # position() over an array of rows
+        ci = np.searchsorted(cs, ii, side="right") - 1
+        cj = np.searchsorted(cs, j, side="right") - 1
+        t_ = np.searchsorted(tkey, ci * nc + cj)
+        assert np.all(tkey[t_] == ci * nc + cj)
+        return to[t_] + (j - cs[cj]) * nf[ci] + (ii - cs[ci])
+
+    for a, b in pairs:
+        ks = np.nonzero(masks[a] & masks[b])[0]
+        pos = positions(ks, rows[b]).astype(np.int64)
+        xk = Xns[torch.from_numpy(pos).cuda()].cpu().numpy()
+        terms = arow[a, ks] * xk
+        r = (1.0 if rows[a] == rows[b] else 0.0) - terms.sum()
+        worst = max(worst, abs(r) / max(np.abs(terms).sum(), 1e-300))
+    print(f"NS: final residual {float(res[-1]):.3e}; {len(pairs)} sampled residual entries, "
+          f"max |r_ij| / sum|A_ik X_kj| = {worst:.3e}", flush=True)
+    assert worst < 1e-10
