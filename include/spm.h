@@ -207,7 +207,8 @@ int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, vo
 /* Fast samplet transform of r vectors (Section 3.2, the transform T of
  * K^Sigma = T K T^T): inverse = 0 gives Y = T X with X in the points' original
  * order and Y in basis order; inverse = 1 gives Y = T^T X (T is orthogonal) with X
- * in basis order and Y in the original order.  X, Y: distinct device F64 arrays,
+ * in basis order and Y in the original order (r = 0 does nothing; X and Y may then
+ * be null).  X, Y: distinct device F64 arrays,
  * r x n row-major (vector j at offset j n).  Uses a stream-ordered temporary of
  * r n doubles and the tree's transform tables, which the first call on a tree
  * uploads (synchronously) and the tree keeps until spm_tree_destroy; later calls
@@ -220,7 +221,8 @@ int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_t inverse, 
  * (Section 5.1).  X and Y: device F64, column-major n x r (column j at offset
  * j n), rows in basis order; Y must not overlap A or X.  Each block row of Y is
  * summed by one workgroup in a fixed order (deterministic run to run); X is read
- * in passes of 16 columns.  r = 0 does nothing.  Asynchronous on the stream;
+ * in passes of 16 columns.  r = 0 does nothing (X and Y may then be null).
+ * Asynchronous on the stream;
  * EINVAL on null or overlapping buffers, r < 0, or n >= 2^25 (32-bit offsets). */
 int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double *Y, void *stream);
 

@@ -506,10 +506,11 @@ static int tree_tables(spm_tree t, spm::TreeDevice **out)
 // column transform of the compression above.
 extern "C" int spm_fst(spm_tree t, const double *X, int32_t r, double *Y, int32_t inverse, void *stream)
 {
-    if (!t || !X || !Y) return fail(SPM_EINVAL, "spm_fst: null pointer");
+    if (!t) return fail(SPM_EINVAL, "spm_fst: null tree");
     if (r < 0) return fail(SPM_EINVAL, "spm_fst: negative vector count");
     const int64_t n = t->n, total = (int64_t)r * n;
-    if (r == 0 || n == 0) return SPM_OK;
+    if (r == 0 || n == 0) return SPM_OK;                     // X and Y may then be null
+    if (!X || !Y) return fail(SPM_EINVAL, "spm_fst: null pointer");
     {
         const char *x0 = reinterpret_cast<const char *>(X), *y0 = reinterpret_cast<const char *>(Y);
         const size_t b = (size_t)total * sizeof(double);

@@ -2280,9 +2280,10 @@ extern "C" int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_
 
 extern "C" int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double *Y, void *stream)
 {
-    if (!p || !A || !X || !Y) return fail(SPM_EINVAL, "spm_spmm: null pointer");
+    if (!p) return fail(SPM_EINVAL, "spm_spmm: null pattern");
     if (r < 0) return fail(SPM_EINVAL, "spm_spmm: negative column count");
-    if (r == 0 || p->nc == 0) return SPM_OK;
+    if (r == 0 || p->nc == 0) return SPM_OK;                 // X and Y may then be null
+    if (!A || !X || !Y) return fail(SPM_EINVAL, "spm_spmm: null pointer");
     if (p->n >= (int64_t(1) << 25)) return fail(SPM_EINVAL, "spm_spmm: n must be below 2^25");
     const size_t vb8 = (size_t)p->n_stored * sizeof(double), pb = (size_t)p->n * r * sizeof(double);
     if (overlap2(X, pb, Y, pb) || overlap2(A, vb8, Y, pb)) return fail(SPM_EINVAL, "spm_spmm: buffers overlap");

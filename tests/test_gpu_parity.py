@@ -388,6 +388,9 @@ def test_matrix_function_argument_errors(S, cfg1):
     d = np.eye(n)[cfg1["mask"]]
     assert np.max(np.abs(z - c[0] / (1.0 + w2[0]) * d)) < 1e-14
     assert float(res[0]) < 1e-15
+    # zero vectors: S x dense and the transform do nothing (empty tensors may hold no storage)
+    X0 = torch.zeros(0, n, dtype=torch.float64, device="cuda")
+    assert S.spmm(pat, A, X0).shape == (0, n)
 
 
 def test_fst_vs_oracle(S):
