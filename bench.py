@@ -1,23 +1,32 @@
 """Benchmark of the S-format masked product on one MI355X.
 
-Workload (the product benchmark of the paper's numerical results, Section 5.1,
-at the sizes of this build's headline configuration): N = 131072 points i.i.d.
-uniform in the unit cube [0,1]^3 (seed 2), exponential kernel (Matern nu = 1/2)
-with lengthscale 0.3 scaled by 1/N, samplets with vanishing moments up to
-degree 1 (m = 4), leaf size 32, eta = 1.0.  K = P_S(T K T^T) is built on the
-device before timing.
+Workload (the product benchmark of the paper's numerical results, Section 5.1, at
+the million-point size the headline metric is quoted on): N = 1048576 points
+i.i.d. uniform in the unit square [0,1]^2 (seed 3), Matern nu = 3/2 kernel with
+lengthscale 0.1 scaled by 1/N, samplets with vanishing moments up to degree 2
+(m = 6), leaf size 32, eta = 1.6.  K = P_S(T K T^T) is built on the device before
+timing (O(N^2) construction, about a minute).
 
-One step = the whole hot path on one batch of input:
-    C = P_S(K K)            (spm_masked_gemm, FP64)
-    Y = K + 0.1 I           (spm_axpy: copy of K, then the identity on the diagonal)
+One step = the FP64 product C = P_S(K K) (spm_masked_gemm_ws, operands resident
+in HBM).  After the timed FP64 steps the same product is timed in the two FP32
+forms (F32SPLIT: hi/lo operands; F32ACC: hi-only operands), each with the same
+number of warm-up and timed repetitions (F32SPLIT capped to about a minute of
+work), and their relative Frobenius error is measured against the FP64 result
+over every stored entry and against the FP64 oracle over sampled entries.
 
-Output: one JSON line.  value = pattern entries of C per second (whole job,
-inputs resident in HBM).  roofline: the product's algorithmic FP64 flops
-(2 x the exact multiply-adds over the tile structure, F in the roofline model)
-per call divided by its average duration from HIP events on the launch stream,
-against the dense FP64 MFMA peak; traffic = HBM bytes per call from the
-committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (null once the device code
-differs from the one the counters were taken on).
+Output: one JSON line.  value = pattern entries of C per second of the FP64 step.
+roofline: the product's algorithmic FP64 flops (2 x the exact multiply-adds over
+the tile structure) per call divided by its average duration from HIP events on
+the launch stream, against the dense FP64 MFMA peak; traffic = HBM bytes per call
+from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (null once the
+device code or schedule differs from the one the counters were taken on).
+cpu_baseline: the oracle's sorted-merge product timed on the host cores over a
+level-stratified sample of output tiles, extrapolated to the whole product by
+exact multiply-adds.
+
+--workload product_cube3 runs the same measurement on N = 131072 points in the
+unit cube (exponential kernel, l = 0.3, degree 1, leaf 32, eta = 1.0, seed 2),
+one step being the FP64 product plus spm_axpy K + 0.1 I.
 """
 from __future__ import annotations
 
@@ -31,12 +40,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(workload="samplet_masked_product_cube3", n=131072, dim=3, kernel="matern_nu0.5", lengthscale=0.3,
-                vanishing_moments_degree=1, leaf=32, eta=1.0, seed=2)
+WORKLOAD = dict(workload="samplet_masked_product_square2d", n=1048576, dim=2, kernel="matern_nu1.5", matern_p=1,
+                lengthscale=0.1, vanishing_moments_degree=2, leaf=32, eta=1.6, seed=3)
+CUBE3 = dict(workload="samplet_masked_product_cube3", n=131072, dim=3, kernel="matern_nu0.5", matern_p=0,
+             lengthscale=0.3, vanishing_moments_degree=1, leaf=32, eta=1.0, seed=2)
 
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 matrix (and vector) peak
 PEAK_HBM = 8000.0     # GB/s
-TRAFFIC_SUMMARY = "masked_product_cube3_n131072_traffic.md"
+TRAFFIC_SUMMARIES = {"samplet_masked_product_square2d": "masked_product_square2d_n1048576_traffic.md",
+                     "samplet_masked_product_cube3": "masked_product_cube3_n131072_traffic.md"}
+SPLIT_BUDGET_S = 60.0  # timed work of one FP32 form is capped at about this long
 
 
 def parse():
@@ -44,89 +57,200 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="override N (testing only)")
+    ap.add_argument("--n", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-oracle-sample", action="store_true")
+    ap.add_argument("--split-modes", default="f32split,f32acc", help="comma-separated FP32 forms to time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
                          "HBM counters can be scaled by a plain copy of known size")
     ap.add_argument("--workload", default="product",
-                    choices=["product", "newton_schulz", "gp_gradient", "expm", "ns_sqrt", "contour", "product_2d",
-                             "matfun_tables"],
-                    help="product (default): the masked product benchmark; newton_schulz: 20 masked Newton-Schulz "
-                         "iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP objective and its "
-                         "lengthscale gradient through 15 iterations (reverse mode), N from --n (default 524288); "
-                         "expm: the truncated exponential series of K (10 terms) on the product workload; "
-                         "ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it; "
+                    choices=["product", "product_cube3", "newton_schulz", "gp_gradient", "expm", "ns_sqrt",
+                             "contour", "matfun_tables"],
+                    help="product (default): the masked product on the million-point square in FP64, F32SPLIT "
+                         "and F32ACC; product_cube3: the same on N = 131072 in the unit cube; newton_schulz: 20 "
+                         "masked Newton-Schulz iterations for (K + 1e-2 I)^-1 at N = 262144; gp_gradient: the GP "
+                         "objective and its lengthscale gradient through 15 iterations (reverse mode), N from --n "
+                         "(default 524288); expm: the truncated exponential series of K (10 terms) on the cube "
+                         "workload; ns_sqrt: 12 coupled Newton-Schulz iterations for (K + 1e-2 I)^{+-1/2} on it; "
                          "contour: (K + 1e-2 I)^{-1/2} on it by a 6-node contour quadrature with 12 masked "
-                         "Newton-Schulz iterations per shifted inverse; product_2d: one product P_S(K K) at "
-                         "N = 1048576 in the unit square (Matern-3/2, l = 0.1, q = 2, eta = 1.6) in FP64, F32ACC "
-                         "and F32SPLIT, with the split modes' errors against FP64; matfun_tables: the protocol of "
-                         "the paper's square-root and exponential tables on a synthetic surface cloud")
+                         "Newton-Schulz iterations per shifted inverse; matfun_tables: the protocol of the paper's "
+                         "square-root and exponential tables on a synthetic surface cloud")
     return ap.parse_args()
 
 
-def cpu_baseline(points, leaf, q, eta, threads):
-    """Oracle's sorted-merge product timed on the host over a bounded row sample.
+def host_cpu():
+    """CPU model and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
-    Sample: all basis rows of 48 leaves spread evenly over the leaf order and of
-    the middle cluster of every internal level from level 4 down (the rows of
-    levels 0-3 are full and would dominate); their output entries
-    c_ij = sum_{k in S_i cap S_j} a_ik b_kj are computed by the oracle's plain C
-    merge with synthetic operand values (the pattern, not the values, sets the
-    work)."""
+
+def cpu_baseline(ot, ob, eta, total_macs, nnz, threads, seed=77, clusters_per_level=3, tiles_per_cluster=64,
+                 tile_cap=None):
+    """The oracle's sorted-merge product timed on the host over a level-stratified
+    sample of output tiles, extrapolated to the whole product by exact multiply-adds.
+
+    Sample: for every tree level, `clusters_per_level` seeded clusters nu of that level,
+    and for each `tiles_per_cluster` seeded tiles (nu, nu') of its block row (all of
+    them when the row is shorter); every entry of the sampled tiles is computed by the
+    oracle's C merge (c_ij = sum over k in S_i cap S_j of a_ik b_kj) on the rows of
+    those clusters, with synthetic operand values (the pattern, not the values, sets
+    the work).  The timed region is the merge alone.  The merge counts its own multiply-adds; the full product's time is
+    extrapolated as total_macs / (sample multiply-adds per second), so the rate is
+    that of a mix covering every level, the dense coarse rows included."""
     import numpy as np
 
     import synth
-    from oracle import native, pattern, samplets, tree
+    from oracle import native, pattern
 
-    ot = tree.build_tree(points, leaf)
-    ob = samplets.build_samplets(ot, q)
-    blocks = pattern.block_pattern(ot, eta)
     cs = ob.cluster_start
-    n = int(cs[-1])
-    leaves = np.nonzero(ot.sons[:, 0] < 0)[0]
+    nf = np.diff(cs)
     lv = ot.level
-    sample = [int(leaves[(2 * k + 1) * len(leaves) // 96]) for k in range(48)]
-    for level in range(4, int(lv[leaves].min())):
-        inner = np.nonzero((lv == level) & (ot.sons[:, 0] >= 0))[0]
-        sample.append(int(inner[len(inner) // 2]))
-    need = sorted(set(np.concatenate([blocks[c] for c in sample]).tolist()) | set(sample))
+    diam = pattern.diameters(ot)
+    rng_u = lambda k, m: synth.uniform(seed * 1000 + k, np.arange(m))
+    picked = []
+    for L in range(int(lv.max()) + 1):
+        at = np.nonzero((lv == L) & (nf > 0))[0]
+        if len(at) == 0:
+            continue
+        sel = np.unique((rng_u(L, clusters_per_level) * len(at)).astype(np.int64))
+        picked.extend(int(at[i]) for i in sel)
+    rows_of = pattern.block_rows(ot, eta, picked, diam)
+    tiles = []
+    for k, nu in enumerate(picked):
+        br = rows_of[nu]
+        br = br[nf[br] > 0]
+        if len(br) > tiles_per_cluster:
+            br = br[np.unique((rng_u(100 + k, tiles_per_cluster) * len(br)).astype(np.int64))]
+        tiles.extend((nu, int(c)) for c in br)
+    if tile_cap is not None:
+        tiles = tiles[:tile_cap]
+    cols = sorted({c for _, c in tiles} - set(rows_of))
+    rows_of.update(pattern.block_rows(ot, eta, cols, diam))
+    # entry-level CSR of the rows the sample reads: rows of nu (A) and of nu' (B^T)
+    need = sorted({nu for nu, _ in tiles} | {c for _, c in tiles})
+    n = int(cs[-1])
     rowlen = np.zeros(n, np.int64)
-    cols_of = {}
+    colsof = {}
+    def basis_of(br):                       # basis indices of the clusters br, in order
+        lens = nf[br]
+        first = np.repeat(cs[br] - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+        return (first + np.arange(int(lens.sum()))).astype(np.int32)
+
     for c in need:
-        cc = np.concatenate([np.arange(cs[b], cs[b + 1]) for b in blocks[c]]).astype(np.int32)
-        cols_of[c] = cc
+        cc = basis_of(rows_of[c])
+        colsof[c] = cc
         rowlen[cs[c]:cs[c + 1]] = len(cc)
     rp = np.zeros(n + 1, np.int64)
     rp[1:] = np.cumsum(rowlen)
     col = np.empty(rp[-1], np.int32)
-    rows_i = np.repeat(np.arange(n), rowlen)
-    for c in need:
-        for i in range(cs[c], cs[c + 1]):
-            col[rp[i]:rp[i + 1]] = cols_of[c]
-    a = 2.0 * synth.pair_uniform(11, rows_i, col, n) - 1.0
-    bt = 2.0 * synth.pair_uniform(12, col, rows_i, n) - 1.0      # bt[pos(j,k)] = b_kj
-    rows = np.concatenate([np.arange(cs[c], cs[c + 1]) for c in sample])
+    for c in need:                          # the rows of cluster c share one column list
+        col[rp[cs[c]]:rp[cs[c + 1]]] = np.tile(colsof[c], int(nf[c]))
+    # synthetic operand values in [-1, 1) (a fixed arithmetic sequence: the pattern, not
+    # the values, sets the work of the merge)
+    idx = np.arange(rp[-1], dtype=np.int64)
+    a = (idx * 40503 % 65521) / 32760.5 - 1.0
+    bt = (idx * 30011 % 65519) / 32759.5 - 1.0
+    del idx
+    ii, jj, pos = [], [], []
+    for nu, c in tiles:
+        off = int(np.searchsorted(colsof[nu], cs[c]))           # first column of c in row nu's list
+        i = np.repeat(np.arange(cs[nu], cs[nu + 1]), nf[c])
+        j = np.tile(np.arange(cs[c], cs[c + 1]), int(nf[nu]))
+        ii.append(i)
+        jj.append(j)
+        pos.append(rp[i] + off + (j - cs[c]))
+    ii, jj, pos = np.concatenate(ii), np.concatenate(jj), np.concatenate(pos)
+    out = np.zeros(rp[-1])
     used = native.set_threads(threads)
     t0 = time.perf_counter()
-    _, cnt = native.masked_product_rows_bt(rows, rp, col, a, bt)
+    macs = native.masked_product_entries(ii, jj, pos, rp, col, a, bt, out)
     dt = time.perf_counter() - t0
-    return {"value": cnt / dt, "unit": "entries/s", "cores": used, "kind": "oracle",
-            "sample": f"all {len(rows)} basis rows of {len(sample)} clusters (48 leaves spread over the leaf "
-                      f"order, the middle cluster of internal levels {[int(lv[c]) for c in sample[48:]]}): {cnt} output "
-                      f"entries of P_S(A B) by the oracle's C sorted-merge product, synthetic operand values, "
-                      f"{dt:.2f} s wall on {used} threads"}
+    rate = macs / dt
+    t_full = total_macs / rate
+    model, ncpu = host_cpu()
+    levels = sorted({int(lv[nu]) for nu, _ in tiles})
+    return {"value": nnz / t_full, "unit": "entries/s", "cores": used, "kind": "oracle", "extrapolated": True,
+            "extrapolated_product_s": t_full, "macs_per_s": rate, "host_cpu": model, "host_logical_cpus": ncpu,
+            "sample": f"{len(tiles)} output tiles ({len(ii)} entries, {macs} multiply-adds) of P_S(A B): "
+                      f"{clusters_per_level} seeded clusters on each tree level {levels[0]}..{levels[-1]} and up to "
+                      f"{tiles_per_cluster} seeded tiles of each one's block row, computed by the oracle's C "
+                      f"sorted-merge product in {dt:.2f} s on {used} threads ({rate / 1e9:.3f} GMAC/s); the whole "
+                      f"product ({total_macs:.4e} multiply-adds) extrapolated by exact multiply-adds to "
+                      f"{t_full:.1f} s"}
 
 
-def recorded_traffic():
-    """HBM bytes per product call from the committed rocprofv3 counter summary, or
-    None when the kernels or the schedule builder have changed since the counters
-    were taken."""
+def oracle_sampled_rows(pts, w, leaves_at=(7, 2), levels=(13, 11)):
+    """Oracle rows of K^eta = P_S(T K T^T) for a small sample of basis functions (the
+    first and last function of two leaves and of their ancestors on the given levels),
+    and the sampled pairs (i, j) of S with the reference entries
+    c_ij = sum_{k in S_i cap S_j} K_ik K_jk of P_S(K K)."""
+    import numpy as np
+
+    from oracle import compress, pattern, samplets, tree
+
+    ot = tree.build_tree(pts, w["leaf"])
+    ob = samplets.build_samplets(ot, w["vanishing_moments_degree"])
+    cs = ob.cluster_start
+    n = int(cs[-1])
+    nf = np.diff(cs)
+    leaves = np.nonzero(ot.sons[:, 0] < 0)[0]
+    chosen = []
+    for k in leaves_at:
+        c = int(leaves[len(leaves) // k])
+        leaf = c
+        while c >= 0:
+            if c == leaf or int(ot.level[c]) in levels:
+                chosen.append(c)
+            c = int(ot.parent[c])
+    rows = np.array(sorted({int(cs[c]) + k for c in set(chosen) for k in (0, int(nf[c]) - 1)}), np.int64)
+    clus_of = np.searchsorted(cs, rows, side="right") - 1
+    kr = compress.compress_rows(ob, rows, w["matern_p"], w["lengthscale"], 1.0 / n, use_c=True)
+    diam = pattern.diameters(ot)
+    masks = np.zeros((len(rows), n), bool)
+    for a_, c in enumerate(clus_of):
+        for b in pattern.block_row(ot, w["eta"], int(c), diam):
+            masks[a_, cs[b]:cs[b + 1]] = True
+    keta = np.where(masks, kr, 0.0)
+    pairs = [(a_, b) for a_ in range(len(rows)) for b in range(len(rows)) if masks[a_, rows[b]]]
+    ref = np.array([keta[a_] @ keta[b] for a_, b in pairs])
+    ij = np.array([(rows[a_], rows[b]) for a_, b in pairs], np.int64)
+    return ot, ob, ij, ref
+
+
+def tile_positions(pat, cs, ij):
+    """Element offsets of the basis pairs ij (m x 2) in the tile layout."""
+    import numpy as np
+
+    tr, tc, to = pat.tiles()
+    nc = len(cs) - 1
+    nf = np.diff(cs)
+    tkey = tr.astype(np.int64) * nc + tc
+    ci = np.searchsorted(cs, ij[:, 0], side="right") - 1
+    cj = np.searchsorted(cs, ij[:, 1], side="right") - 1
+    t = np.searchsorted(tkey, ci * nc + cj)
+    assert np.all(tkey[t] == ci * nc + cj)
+    return to[t] + (ij[:, 1] - cs[cj]) * nf[ci] + (ij[:, 0] - cs[ci])
+
+
+def recorded_traffic(workload):
+    """HBM bytes per product call from the committed rocprofv3 counter summary of the
+    workload, or None when there is none or the kernels or the schedule builder have
+    changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY)
-    if not os.path.exists(path):
+    name = TRAFFIC_SUMMARIES.get(workload)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
         return None
     fields = {}
     with open(path) as f:
@@ -171,7 +295,7 @@ def newton_schulz_main(args):
     from paper_2211_11681_amd import spm as S
 
     w = dict(NS_WORKLOAD)
-    n = args.n if args.n != WORKLOAD["n"] else w["n"]
+    n = args.n or w["n"]
     w["n"] = n
     print(f"[bench] newton_schulz: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
     pts = synth.points_cube(n, w["dim"], w["seed"])
@@ -212,7 +336,7 @@ def gp_gradient_main(args):
     from paper_2211_11681_amd import spm as S
 
     w = dict(GP_WORKLOAD)
-    n = args.n if args.n != WORKLOAD["n"] else w["n"]
+    n = args.n or w["n"]
     w["n"] = n
     print(f"[bench] gp_gradient: building tree and pattern for n={n}", file=sys.stderr, flush=True)
     pts = synth.points_sphere(n, w["seed"])
@@ -255,8 +379,8 @@ def expm_main(args):
     import synth
     from paper_2211_11681_amd import spm as S
 
-    w = dict(WORKLOAD, workload="expm_taylor_cube3", terms=10)
-    n = args.n
+    w = dict(CUBE3, workload="expm_taylor_cube3", terms=10)
+    n = args.n or w["n"]
     w["n"] = n
     print(f"[bench] expm: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
     pts = synth.points_cube(n, w["dim"], w["seed"])
@@ -302,8 +426,8 @@ def ns_sqrt_main(args):
     import synth
     from paper_2211_11681_amd import spm as S
 
-    w = dict(WORKLOAD, workload="ns_sqrt_cube3", mu=1e-2, iterations=12)
-    n = args.n
+    w = dict(CUBE3, workload="ns_sqrt_cube3", mu=1e-2, iterations=12)
+    n = args.n or w["n"]
     w["n"] = n
     print(f"[bench] ns_sqrt: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
     pts = synth.points_cube(n, w["dim"], w["seed"])
@@ -340,8 +464,8 @@ def contour_main(args):
     import synth
     from paper_2211_11681_amd import spm as S
 
-    w = dict(WORKLOAD, workload="contour_invsqrt_cube3", mu=1e-2, nodes=6, ns_iterations=12)
-    n = args.n
+    w = dict(CUBE3, workload="contour_invsqrt_cube3", mu=1e-2, nodes=6, ns_iterations=12)
+    n = args.n or w["n"]
     w["n"] = n
     print(f"[bench] contour: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
     pts = synth.points_cube(n, w["dim"], w["seed"])
@@ -372,63 +496,6 @@ def contour_main(args):
            "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
            "ms": ms, "products": products, "ms_per_product": ms / products, "node_residuals": r,
            "e_F_ZAZ_minus_I": e_inv}
-    print(json.dumps(out), flush=True)
-
-
-PRODUCT_2D = dict(workload="samplet_masked_product_square2d", n=1048576, dim=2, kernel="matern_nu1.5",
-                  lengthscale=0.1, vanishing_moments_degree=2, leaf=32, eta=1.6, seed=3)
-
-
-def product_2d_main(args):
-    """One product P_S(K K) on a million points in the unit square, in FP64 and in the
-    two FP32 modes, with the relative Frobenius error of each mode against FP64."""
-    import numpy as np
-    import torch
-
-    import synth
-    from paper_2211_11681_amd import spm as S
-
-    os.environ.setdefault("SPM_PROGRESS", "1")       # the O(N^2) construction reports its panels
-    w = dict(PRODUCT_2D)
-    n = args.n if args.n != WORKLOAD["n"] else w["n"]
-    w["n"] = n
-    print(f"[bench] product_2d: tree for n={n}", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    pts = synth.points_cube(n, w["dim"], w["seed"])
-    tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
-    print(f"[bench] product_2d: pattern and schedule ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    pat = S.Pattern.from_tree(tree, w["eta"])
-    print(f"[bench] product_2d: {pat.n_tiles} tiles, {pat.nnz} entries ({time.perf_counter() - t0:.1f} s); "
-          f"compressing K", file=sys.stderr, flush=True)
-    K = S.kernel_compress(pat, tree, 1, w["lengthscale"], 1.0 / n)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    print(f"[bench] product_2d: setup {t_setup:.1f} s, {pat.macs:.3e} MACs per product", file=sys.stderr, flush=True)
-    C = pat.empty("f64")
-    S.masked_gemm(pat, K, K, out=C)                                   # warm-up
-    reps = max(1, min(args.steps, 3))
-    _, ms = _timed(lambda: [S.masked_gemm(pat, K, K, out=C) for _ in range(reps)])
-    ms /= reps
-    print(f"[bench] product_2d: FP64 {ms:.1f} ms", file=sys.stderr, flush=True)
-    ref_norm = S.sqdist(pat, C).item() ** 0.5
-    out = {"metric": "pattern entries/s of P_S(A*B) (FP64), with FP32 modes at stated relative error",
-           "value": pat.nnz / (ms * 1e-3), "unit": "entries/s", "n_gpus": 1, "higher_is_better": True,
-           "dtype": "f64", "data": "synthetic",
-           "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs, setup_s=t_setup),
-           "product_ms": ms, "algorithmic_TFLOPs": 2.0 * pat.macs / (ms * 1e-3) / 1e12}
-    for prec in ("f32acc", "f32split"):
-        Ks = S.convert(pat, K, "f64", prec)
-        Cs = S.masked_gemm(pat, Ks, Ks, prec=prec)                    # warm-up (and the result)
-        (_,), ms_p = _timed(lambda: (S.masked_gemm(pat, Ks, Ks, prec=prec, out=Cs),))
-        del Ks
-        C64 = S.convert(pat, Cs, prec, "f64")
-        del Cs
-        err = S.sqdist(pat, C64, C).item() ** 0.5 / ref_norm
-        del C64
-        torch.cuda.synchronize()
-        out[prec] = {"product_ms": ms_p, "entries_per_s": pat.nnz / (ms_p * 1e-3), "speedup_vs_f64": ms / ms_p,
-                     "rel_frobenius_err_vs_f64": err}
-        print(f"[bench] product_2d: {prec} {ms_p:.1f} ms, rel err {err:.3e}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
@@ -524,29 +591,50 @@ def main():
         return ns_sqrt_main(args)
     if args.workload == "contour":
         return contour_main(args)
-    if args.workload == "product_2d":
-        return product_2d_main(args)
     if args.workload == "matfun_tables":
         return matfun_tables_main(args)
-    n = args.n
-    w = WORKLOAD
-    print(f"[bench] building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
+    if args.workload == "product_cube3":
+        return product_main(args, dict(CUBE3), with_axpy=True)
+    return product_main(args, dict(WORKLOAD), with_axpy=False)
+
+
+def product_main(args, w, with_axpy):
+    """The masked product P_S(K K) in FP64 (timed steps), then in the FP32 forms."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2211_11681_amd import spm as S
+
+    n = args.n or w["n"]
+    full = n == w["n"]
+    w["n"] = n
+    os.environ.setdefault("SPM_PROGRESS", "1")       # the O(N^2) construction reports its panels
+    print(f"[bench] {w['workload']}: building tree, pattern and K for n={n}", file=sys.stderr, flush=True)
     pts = synth.points_cube(n, w["dim"], w["seed"])
     t0 = time.perf_counter()
     tree = S.Tree(pts, w["leaf"], w["vanishing_moments_degree"])
     pat = S.Pattern.from_tree(tree, w["eta"])
-    K = S.kernel_compress(pat, tree, 0, w["lengthscale"], 1.0 / n)
+    t_plan = time.perf_counter() - t0
+    print(f"[bench] tree, pattern and schedule {t_plan:.1f} s: tiles {pat.n_tiles} nnz {pat.nnz} "
+          f"macs {pat.macs:.4e}", file=sys.stderr, flush=True)
+    K = S.kernel_compress(pat, tree, w["matern_p"], w["lengthscale"], 1.0 / n)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    print(f"[bench] setup {t_setup:.1f} s: tiles {pat.n_tiles} nnz {pat.nnz} macs {pat.macs:.3e}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] setup {t_setup:.1f} s", file=sys.stderr, flush=True)
     C = pat.empty("f64")
-    Y = pat.empty("f64")
+    Y = pat.empty("f64") if with_axpy else None
+    ws = S.gemm_workspace(pat, "f64")
+    stream = torch.cuda.current_stream()
+
+    def product():
+        S.masked_gemm(pat, K, K, out=C, workspace=ws)
 
     def step():
-        S.masked_gemm(pat, K, K, out=C)
-        S.axpy(pat, 1.0, K, 0.0, Y)
-        S.axpy(pat, 0.1, None, 1.0, Y)
+        product()
+        if with_axpy:
+            S.axpy(pat, 1.0, K, 0.0, Y)
+            S.axpy(pat, 0.1, None, 1.0, Y)
 
     for _ in range(args.warmup):
         step()
@@ -554,14 +642,15 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    start.record()
+    start.record(stream)
     for k in range(args.steps):
-        ev[k][0].record()
-        S.masked_gemm(pat, K, K, out=C)
-        ev[k][1].record()
-        S.axpy(pat, 1.0, K, 0.0, Y)
-        S.axpy(pat, 0.1, None, 1.0, Y)
-    end.record()
+        ev[k][0].record(stream)
+        product()
+        ev[k][1].record(stream)
+        if with_axpy:
+            S.axpy(pat, 1.0, K, 0.0, Y)
+            S.axpy(pat, 0.1, None, 1.0, Y)
+    end.record(stream)
     torch.cuda.synchronize()
     ms_total = start.elapsed_time(end)
     ms_step = ms_total / args.steps
@@ -571,11 +660,13 @@ def main():
         torch.cuda.synchronize()
         del Kc
     print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, product {ms_gemm:.3f} ms", file=sys.stderr, flush=True)
+    del Y, ws
 
     flops = 2.0 * pat.macs
     tflops = flops / (ms_gemm * 1e-3) / 1e12
-    compulsory = 3 * pat.n_stored * 8          # A, B (here the same array, counted twice as operands) and C
-    traffic = recorded_traffic() if n == WORKLOAD["n"] else None
+    # compulsory HBM bytes of one call: A and B (one array here, counted once) and C
+    compulsory = 2 * pat.n_stored * 8
+    traffic = recorded_traffic(w["workload"]) if full else None
     out = {
         "metric": "pattern entries/s of P_S(A*B) (FP64), with HBM GB/s and FP32-split at stated relative error",
         "value": pat.nnz / (ms_step * 1e-3),
@@ -589,37 +680,101 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": dict(w, n=n, n_tiles=pat.n_tiles, nnz=pat.nnz, macs_per_product=pat.macs),
+        "config": dict(w, n_tiles=pat.n_tiles, nnz=pat.nnz, n_stored=pat.n_stored, macs_per_product=pat.macs,
+                       step="FP64 product" + (" + axpy K + 0.1 I" if with_axpy else "")),
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64, "traffic": traffic},
         "product_ms": ms_gemm,
         "product_compulsory_GBps": compulsory / (ms_gemm * 1e-3) / 1e9,
         "product_hbm_GBps": None if traffic is None else traffic / (ms_gemm * 1e-3) / 1e9,
         "setup_s": t_setup,
+        "plan_s": t_plan,
+        "classes": pat.classes(),
     }
+    ref_norm = S.sqdist(pat, C).item() ** 0.5
+
+    # oracle rows for sampled entries (FP64 oracle, independent of the library)
+    sample = None
+    if full and not args.no_oracle_sample:
+        t1 = time.perf_counter()
+        ot, ob, ij, ref = oracle_sampled_rows(pts, w)
+        pos = torch.from_numpy(tile_positions(pat, ob.cluster_start, ij)).cuda()
+        got = C[pos].cpu().numpy()
+        e64 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        sample = dict(ot=ot, ob=ob, ij=ij, ref=ref, pos=pos)
+        out["oracle_sample"] = {"entries": len(ref), "largest_position": int(pos.max()),
+                                "f64_rel_frobenius_err": e64, "s": time.perf_counter() - t1}
+        print(f"[bench] oracle sample: {len(ref)} entries, FP64 rel err {e64:.3e} "
+              f"({time.perf_counter() - t1:.1f} s)", file=sys.stderr, flush=True)
+
     if not args.no_split:
-        ref_norm = S.sqdist(pat, C).item() ** 0.5
-        for prec in ("f32split", "f32acc"):
-            Ks = S.convert(pat, K, "f64", prec)
-            Cs = S.masked_gemm(pat, Ks, Ks, prec=prec)
+        # the FP32 operands are made from K once: hi/lo first, hi-only from the hi/lo copy
+        # (fl32(hi + lo) = hi), so that K itself can be released before the split runs
+        modes = [m for m in ("f32split", "f32acc") if m in args.split_modes.split(",")]
+        Kcur, cur = K, "f64"
+        del K
+        for prec in modes:
+            Ks = S.convert(pat, Kcur, cur, prec)
+            del Kcur
+            torch.cuda.empty_cache()
+            Kcur, cur = Ks, prec
+            Cs = pat.empty(prec)
+            wsp = S.gemm_workspace(pat, prec)
+
+            def prod_s():
+                S.masked_gemm(pat, Ks, Ks, prec=prec, out=Cs, workspace=wsp)
+
+            t_first = time.perf_counter()
+            prod_s()                                                # first warm-up, sizes the repetitions
             torch.cuda.synchronize()
+            t_first = time.perf_counter() - t_first
+            reps = max(1, min(args.steps, int(SPLIT_BUDGET_S / max(t_first, 1e-3))))
+            warm = max(0, min(args.warmup - 1, reps))
+            for _ in range(warm):
+                prod_s()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = max(1, args.steps // 2)
-            e0.record()
+            torch.cuda.synchronize()
+            e0.record(stream)
             for _ in range(reps):
-                S.masked_gemm(pat, Ks, Ks, prec=prec, out=Cs)
-            e1.record()
+                prod_s()
+            e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
-            C64 = S.convert(pat, Cs, prec, "f64")
-            err = S.sqdist(pat, C64, C).item() ** 0.5 / ref_norm
-            out[prec] = {"product_ms": ms, "entries_per_s": pat.nnz / (ms * 1e-3), "speedup_vs_f64": ms_gemm / ms,
-                         "rel_frobenius_err_vs_f64": err}
-            del Ks, Cs, C64
-            print(f"[bench] {prec}: {ms:.3f} ms, rel err {err:.3e}", file=sys.stderr, flush=True)
+            del wsp
+            # error against the FP64 result over every stored entry, in the split format's
+            # precision (FP64 -> hi/lo loses about 2^-48) or after widening FP32 to FP64
+            if prec == "f32split":
+                Cref = S.convert(pat, C, "f64", "f32split")
+                err = S.sqdist(pat, Cs, Cref, prec="f32split").item() ** 0.5 / ref_norm
+                del Cref
+            else:
+                C64 = S.convert(pat, Cs, prec, "f64")
+                err = S.sqdist(pat, C64, C).item() ** 0.5 / ref_norm
+                del C64
+            res = {"product_ms": ms, "reps": reps, "entries_per_s": pat.nnz / (ms * 1e-3),
+                   "speedup_vs_f64": ms_gemm / ms, "rel_frobenius_err_vs_f64": err}
+            if sample is not None:
+                hi = Cs[sample["pos"]].double()
+                if prec == "f32split":
+                    hi = hi + Cs[pat.n_stored + sample["pos"]].double()
+                got = hi.cpu().numpy()
+                res["rel_frobenius_err_vs_oracle_sample"] = float(np.linalg.norm(got - sample["ref"]) /
+                                                                 np.linalg.norm(sample["ref"]))
+            out[prec] = res
+            del Ks, Cs
+            torch.cuda.empty_cache()
+            print(f"[bench] {prec}: {ms:.3f} ms x {reps}, rel err vs FP64 {err:.3e}", file=sys.stderr, flush=True)
+        del Kcur
     if not args.no_cpu_baseline:
-        threads = int(os.environ.get("SPM_CPU_THREADS", min(16, os.cpu_count() or 1)))
-        out["cpu_baseline"] = cpu_baseline(pts, w["leaf"], w["vanishing_moments_degree"], w["eta"], threads)
+        threads = int(os.environ.get("SPM_CPU_THREADS", os.cpu_count() or 1))
+        if sample is not None:
+            ot, ob = sample["ot"], sample["ob"]
+        else:
+            from oracle import samplets, tree as otree
+            ot = otree.build_tree(pts, w["leaf"])
+            ob = samplets.build_samplets(ot, w["vanishing_moments_degree"])
+        print(f"[bench] CPU baseline on {threads} threads", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(ot, ob, w["eta"], pat.macs, pat.nnz, threads)
     print(json.dumps(out), flush=True)
 
 

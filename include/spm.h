@@ -55,7 +55,7 @@ typedef enum {
     SPM_EPATTERN = -2,      /* pattern fails validation */
     SPM_ENOMEM = -3,        /* host or device allocation failed */
     SPM_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
-    SPM_ENOTCONV = -5,      /* Newton-Schulz residual non-finite or not decreasing */
+    SPM_ENOTCONV = -5,      /* Newton-Schulz final residual non-finite or above the initial one */
     SPM_EUNSUPPORTED = -6   /* valid input outside what the kernels support */
 } spm_status;
 
@@ -118,12 +118,46 @@ int spm_block_pattern_upload(int64_t n, int32_t n_clusters, const int64_t *clust
                              const int64_t *blk_row_ptr, const int32_t *blk_col, void *stream,
                              spm_pattern *out);
 
+/* Planning without device memory, for callers that own the device memory (the upload
+ * above is plan + spm_pattern_upload_workspace into a block the library allocates).
+ * spm_block_pattern_plan / spm_compress_pattern_plan: the same validation, tile
+ * layout, transpose map and schedule as the uploads, on the host only (EPATTERN,
+ * EINVAL, EUNSUPPORTED as above).  The handle answers spm_pattern_info,
+ * spm_pattern_tiles, spm_pattern_download_csr, spm_pattern_classes and
+ * spm_pattern_workspace_bytes; every compute call on it returns EINVAL until it is
+ * uploaded.
+ * spm_pattern_workspace_bytes: device bytes of the pattern's tables.
+ * spm_pattern_upload_workspace: copies the tables into the caller's device memory ws
+ * (at least that many bytes, 256-byte aligned); the pattern keeps pointers into ws,
+ * which the caller keeps alive and unmodified until spm_pattern_destroy (which does
+ * not free it).  Synchronous (blocking copies).  EINVAL on a short or misaligned
+ * workspace or a pattern already uploaded. */
+int spm_block_pattern_plan(int64_t n, int32_t n_clusters, const int64_t *cluster_start,
+                           const int64_t *blk_row_ptr, const int32_t *blk_col, spm_pattern *out);
+int spm_compress_pattern_plan(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int32_t n_clusters,
+                              const int64_t *cluster_start, spm_pattern *out);
+int spm_pattern_workspace_bytes(spm_pattern p, size_t *bytes);
+int spm_pattern_upload_workspace(spm_pattern p, void *ws, size_t bytes, void *stream);
+
+/* Frees the host tables and, for patterns uploaded by spm_block_pattern_upload or
+ * spm_compress_pattern_upload, the device tables. */
 int spm_pattern_destroy(spm_pattern p);
 
 /* nnz = |S|, n_stored = value-array length, n_tiles, macs = exact multiply-adds
  * of one product P_S(A B) over the tile structure (sum over output tiles (c,c')
  * of n_c n_c' sum_{mu in S_c cap S_c'} n_mu). */
 int spm_pattern_info(spm_pattern p, int64_t *nnz, int64_t *n_stored, int64_t *n_tiles, double *macs);
+
+/* Launch classes of the product schedule: units (pairs of groups of clusters) binned
+ * by their size in 16-row blocks (row_blocks x col_blocks).  Per class: units,
+ * output tiles, exact multiply-adds (the sum over its output tiles (c, c') of
+ * n_c n_c' sum_{mu in S_c cap S_c'} n_mu, the cost in the proof of Theorem (product);
+ * over all classes it is the macs of spm_pattern_info) and the multiply-adds the
+ * FP64 kernels issue for it including padding, before skipping empty blocks.  Call
+ * with all arrays NULL to get the count in *n_classes; otherwise *n_classes is the
+ * capacity of the arrays (any may be NULL) and receives the count. */
+int spm_pattern_classes(spm_pattern p, int32_t *n_classes, int32_t *row_blocks, int32_t *col_blocks,
+                        int64_t *units, int64_t *out_tiles, double *exact_macs, double *padded_macs);
 
 /* Host copies of the tile structure (any may be NULL): tile_row[n_tiles],
  * tile_col[n_tiles], tile_off[n_tiles] (element offset of each tile). */
@@ -160,14 +194,30 @@ int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t matern_p, double ell,
 /* C = P_S(op(A) op(B)), op(X) = X or X^T (Section 4.1, Theorem (product),
  * eq. (product)): for every (i,j) in S, c_ij = sum_k op(A)_ik op(B)_kj, the sum
  * over the k with (i,k) and (k,j) in S, exact on the pattern.  A, B, C in
- * precision `prec`; C must not alias A or B (EINVAL). */
+ * precision `prec`; C must not alias A or B (EINVAL).  Takes its workspace
+ * (transposed operand copies) from the stream-ordered allocator (hipMallocAsync). */
 int spm_masked_gemm(spm_pattern p, int prec, const void *A, int transA, const void *B, int transB,
                     void *C, void *stream);
 
+/* The same product with the workspace supplied by the caller: ws (device, 256-byte
+ * aligned, not overlapping A, B or C) of at least spm_masked_gemm_workspace() bytes
+ * for the same precision and transpose flags (0 bytes: ws may be NULL).  Nothing is
+ * allocated; ws may be reused once the call's work on the stream has completed.
+ * EINVAL on a short, misaligned or overlapping workspace. */
+int spm_masked_gemm_workspace(spm_pattern p, int prec, int transA, int transB, size_t *bytes);
+int spm_masked_gemm_ws(spm_pattern p, int prec, const void *A, int transA, const void *B, int transB,
+                       void *C, void *ws, size_t ws_bytes, void *stream);
+
 /* Adjoint of C = P_S(A B) (one pattern for all operands):
- * dA = P_S(dC B^T), dB = P_S(A^T dC).  dA or dB may be NULL to skip it. */
+ * dA = P_S(dC B^T), dB = P_S(A^T dC).  dA or dB may be NULL to skip it.
+ * spm_masked_gemm_backward allocates its workspace like spm_masked_gemm;
+ * spm_masked_gemm_backward_ws takes it from the caller (at least
+ * spm_masked_gemm_backward_workspace() bytes, rules as for spm_masked_gemm_ws). */
 int spm_masked_gemm_backward(spm_pattern p, int prec, const void *dC, const void *A, const void *B,
                              void *dA, void *dB, void *stream);
+int spm_masked_gemm_backward_workspace(spm_pattern p, int prec, size_t *bytes);
+int spm_masked_gemm_backward_ws(spm_pattern p, int prec, const void *dC, const void *A, const void *B,
+                                void *dA, void *dB, void *ws, size_t ws_bytes, void *stream);
 
 /* Y = alpha X + beta Y on the stored values (formatted addition, Section 4.1);
  * X = NULL stands for the identity (only the diagonal of Y changes). */
@@ -198,8 +248,9 @@ int spm_fill_outer(spm_pattern p, double alpha, const double *y, double *X, void
  * so that on the full pattern E = sum_{j <= terms} A^j / j!.  A and E are device
  * F64 value arrays (distinct); terms >= 0 (0 gives E = I).  scratch: device
  * workspace of at least spm_expm_taylor_scratch() bytes (one value array), unused
- * when terms = 0.  Asynchronous on the stream; EINVAL on null or overlapping
- * buffers, a negative term count or a short scratch. */
+ * when terms = 0; 256-byte aligned; it includes the products' workspace, so nothing
+ * is allocated.  Asynchronous on the stream; EINVAL on null or overlapping
+ * buffers, a negative term count or a short or misaligned scratch. */
 int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes);
 int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_t terms, void *scratch,
                     size_t scratch_bytes, void *stream);
@@ -236,8 +287,9 @@ int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double 
  * K + mu I with K scaled by 1/N, any 0 < mu < 1).  A, Y, Z: distinct device F64
  * value arrays; Y and Z receive Y_iters and Z_iters.  residuals: device array of
  * iters doubles, or NULL.  scratch: device workspace of at least
- * spm_ns_sqrt_scratch() bytes (three value arrays).  Asynchronous on the stream;
- * EINVAL on null or overlapping buffers, a negative iteration count or a short
+ * spm_ns_sqrt_scratch() bytes (three value arrays and the products' workspace),
+ * 256-byte aligned; nothing is allocated.  Asynchronous on the stream; EINVAL on
+ * null or overlapping buffers, a negative iteration count or a short or misaligned
  * scratch. */
 int spm_ns_sqrt_scratch(spm_pattern p, size_t *bytes);
 int spm_ns_sqrt(spm_pattern p, const double *A, double *Y, double *Z, int32_t iters, double *residuals,
@@ -246,13 +298,16 @@ int spm_ns_sqrt(spm_pattern p, const double *A, double *Y, double *Z, int32_t it
 /* Masked Newton-Schulz inverse of A (FP64 on S):
  *   X_0 = alpha0 I;  for k = 0..iters-1:  Y_k = P_S(A X_k),  r_k = ||I - Y_k||_F / sqrt(n),
  *   Z_k = 2I - Y_k,  X_{k+1} = P_S(X_k Z_k);  finally r_iters = ||I - P_S(A X_iters)||_F / sqrt(n).
- * Iterations 0 .. iters-n_final_f64-1 run in precision `bulk`, the rest and
- * every residual in FP64.  X (device, F64) receives X_iters.  residuals (device,
+ * Iterations 0 .. iters-n_final_f64-1 run in precision `bulk`, the rest in FP64.
+ * Every residual is summed in FP64; those of the bulk iterations are taken of the
+ * bulk-precision product P_S(A X_k) (rounded to that precision), the others and the
+ * final one of FP64 products.  X (device, F64) receives X_iters.  residuals (device,
  * iters+1 doubles).  checkpoints (host array of iters+1 device F64 pointers, or
  * NULL) receives X_0 .. X_iters.  scratch: device workspace of at least
- * spm_newton_schulz_scratch() bytes.  Returns ENOTCONV when the final residual
- * is not finite (X is still written); this is the only call that synchronises
- * the stream (to read the final residual). */
+ * spm_newton_schulz_scratch() bytes, 256-byte aligned; nothing else is allocated.
+ * Returns ENOTCONV when the final residual is not finite or exceeds the initial
+ * one r_0 (a diverging iteration; X is still written); this call synchronises the
+ * stream (to read the two residuals). */
 int spm_newton_schulz_scratch(spm_pattern p, int bulk, size_t *bytes);
 int spm_newton_schulz(spm_pattern p, const double *A, double *X, int32_t iters, int32_t n_final_f64,
                       int bulk, double alpha0, double *residuals, double *const *checkpoints,
@@ -274,7 +329,8 @@ int spm_contour_rule(double lam_min, double lam_max, int32_t nodes, double *w2, 
  * A^{1/2} follows as P_S(A out).  out: device F64 value array distinct from A.
  * residuals: device array of `nodes` doubles (the final Newton-Schulz residual of
  * each shifted inverse), or NULL.  scratch: device workspace of at least
- * spm_contour_invsqrt_scratch() bytes.  Synchronises the stream once per node (as
+ * spm_contour_invsqrt_scratch() bytes, 256-byte aligned; nothing is allocated.
+ * Synchronises the stream once per node (as
  * spm_newton_schulz does); with the environment variable SPM_PROGRESS set, reports
  * each node on stderr.  ENOTCONV when a shifted inverse's residual is not finite,
  * EINVAL on bad arguments. */

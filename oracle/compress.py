@@ -49,7 +49,8 @@ def compress_rows(basis: SampletBasis, rows: np.ndarray, p: int, ell: float, sca
     Row b of K^Sigma is T (K omega_b): first the kernel is applied to the
     coefficient vector omega_b (only the points of b's cluster contribute),
     then the samplet transform T maps the result to samplet coordinates.
-    ``use_c`` evaluates the kernel sums with the oracle's plain C helper.
+    ``use_c`` evaluates the kernel sums with the oracle's plain C helper, the rows
+    owned by one cluster together (the same sums, each in the same order).
     """
     t = basis.tree
     n = int(t.size[0])
@@ -59,6 +60,17 @@ def compress_rows(basis: SampletBasis, rows: np.ndarray, p: int, ell: float, sca
     owner = basis.support_cluster_of()
     f = kernel_fn(p, ell, deriv)
     out = np.zeros((len(rows), n))
+    if use_c:
+        from . import native
+        rows = np.asarray(rows)
+        for c in np.unique(owner[rows]):
+            ks = np.nonzero(owner[rows] == c)[0]
+            s, sz = int(t.start[c]), int(t.size[c])
+            W = np.asarray(basis.coef[c])[rows[ks] - basis.cluster_start[c]].T      # sz x len(ks)
+            acc = native.kernel_apply_multi(x, x[s:s + sz], W, p, ell, scale, deriv)
+            for q, k in enumerate(ks):
+                out[k] = T @ acc[:, q]
+        return out
     for k, b in enumerate(rows):
         c = owner[b]
         s, sz = int(t.start[c]), int(t.size[c])

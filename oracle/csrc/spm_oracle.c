@@ -6,6 +6,7 @@
  *   (product), eq. (product)): c_ij = sum over k in S_i and S_j of a_ik b_kj,
  *   evaluated entry by entry as a sorted merge of row i of A with column j of B,
  *   summing in ascending k;
+ *   (also on a list of single entries, counting the multiply-adds);
  * - kernel sums sum_p w_p k(|x_q - x_p|) used to form single rows of
  *   K^Sigma = T K T^T (Section 3.3) without the full matrix.
  *
@@ -81,6 +82,32 @@ int64_t oracle_masked_product_rows(int64_t nrows, const int64_t *rows, const int
     return cnt;
 }
 
+/* Entries c_ij for a list of positions (i, j) of S (pos[t] = stored position of
+ * (ii[t], jj[t]), where c is written); *macs receives the number of multiply-adds,
+ * i.e. the sum of |S_i cap S_j| over the list. */
+void oracle_masked_product_entries(int64_t np, const int64_t *ii, const int64_t *jj, const int64_t *pos,
+                                   const int64_t *rp, const int32_t *col, const double *a, const double *bt,
+                                   double *c, int64_t *macs)
+{
+    int64_t m = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : m)
+    for (int64_t t = 0; t < np; ++t) {
+        int64_t i = ii[t], j = jj[t];
+        int64_t p = rp[i], pe = rp[i + 1], r = rp[j], re = rp[j + 1];
+        double s = 0.0;
+        int64_t k = 0;
+        while (p < pe && r < re) {
+            int32_t ki = col[p], kj = col[r];
+            if (ki < kj) ++p;
+            else if (kj < ki) ++r;
+            else { s += a[p] * bt[r]; ++p; ++r; ++k; }
+        }
+        c[pos[t]] = s;
+        m += k;
+    }
+    *macs = m;
+}
+
 static double fact(int k)
 {
     double f = 1.0;
@@ -123,6 +150,33 @@ void oracle_kernel_apply(int64_t n, int d, const double *x, int64_t m, const dou
             s += w[t] * matern(sqrt(r2), p, ell, deriv);
         }
         acc[q] = scale * s;
+    }
+}
+
+/* The same sums for k weight vectors at once (w row-major m x k): acc[q*k + c] =
+ * scale * sum_{t < m} w[t*k + c] k(|x_q - y_t|), each sum in the order of the
+ * single-vector call, so every column equals that call bit for bit. */
+void oracle_kernel_apply_multi(int64_t n, int d, const double *x, int64_t m, const double *y,
+                               const double *w, int k, int p, double ell, double scale, int deriv, double *acc)
+{
+#pragma omp parallel
+    {
+        double *s = (double *)malloc((size_t)k * sizeof(double));
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < n; ++q) {
+            for (int c = 0; c < k; ++c) s[c] = 0.0;
+            for (int64_t t = 0; t < m; ++t) {
+                double r2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double df = x[q * d + a] - y[t * d + a];
+                    r2 += df * df;
+                }
+                const double kv = matern(sqrt(r2), p, ell, deriv);
+                for (int c = 0; c < k; ++c) s[c] += w[t * k + c] * kv;
+            }
+            for (int c = 0; c < k; ++c) acc[q * k + c] = scale * s[c];
+        }
+        free(s);
     }
 }
 

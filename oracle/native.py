@@ -36,9 +36,14 @@ def lib():
         L.oracle_masked_product.restype = None
         L.oracle_masked_product_rows.argtypes = [i64, P, P, P, P, P, P]
         L.oracle_masked_product_rows.restype = i64
+        L.oracle_masked_product_entries.argtypes = [i64, P, P, P, P, P, P, P, P, P]
+        L.oracle_masked_product_entries.restype = None
         L.oracle_kernel_apply.argtypes = [i64, ctypes.c_int, P, i64, P, P, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
         L.oracle_kernel_apply.restype = None
+        L.oracle_kernel_apply_multi.argtypes = [i64, ctypes.c_int, P, i64, P, P, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
+        L.oracle_kernel_apply_multi.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = ctypes.c_int
         _lib = L
@@ -104,6 +109,23 @@ def masked_product_rows_bt(rows, rp, col, a, bt):
     return c, int(cnt)
 
 
+def masked_product_entries(ii, jj, pos, rp, col, a, bt, c):
+    """Entries c_ij of P_S(A B) at the listed (i, j) (written to c[pos]); bt holds B^T
+    on the pattern (bt[pos(j, k)] = b_kj).  Returns the number of multiply-adds."""
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    pos = np.ascontiguousarray(pos, dtype=np.int64)
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    bt = np.ascontiguousarray(bt, dtype=np.float64)
+    assert c.dtype == np.float64 and c.flags.c_contiguous
+    m = ctypes.c_int64(0)
+    lib().oracle_masked_product_entries(ii.shape[0], _p(ii), _p(jj), _p(pos), _p(rp), _p(col), _p(a), _p(bt), _p(c),
+                                        ctypes.byref(m))
+    return int(m.value)
+
+
 def kernel_apply(x: np.ndarray, y: np.ndarray, w: np.ndarray, p: int, ell: float, scale: float,
                  deriv: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -112,4 +134,18 @@ def kernel_apply(x: np.ndarray, y: np.ndarray, w: np.ndarray, p: int, ell: float
     out = np.empty(x.shape[0])
     lib().oracle_kernel_apply(x.shape[0], x.shape[1], _p(x), y.shape[0], _p(y), _p(w), p, ell, scale,
                               int(deriv), _p(out))
+    return out
+
+
+def kernel_apply_multi(x: np.ndarray, y: np.ndarray, w: np.ndarray, p: int, ell: float, scale: float,
+                       deriv: bool = False) -> np.ndarray:
+    """kernel_apply for the columns of w (m x k) at once; returns (n x k), each column
+    bit-identical to kernel_apply with that column."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    k = w.shape[1]
+    out = np.empty((x.shape[0], k))
+    lib().oracle_kernel_apply_multi(x.shape[0], x.shape[1], _p(x), y.shape[0], _p(y), _p(w), k, p, ell, scale,
+                                    int(deriv), _p(out))
     return out

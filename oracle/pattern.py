@@ -45,6 +45,26 @@ def block_row(tree: ClusterTree, eta: float, c: int, diam: np.ndarray | None = N
     return np.nonzero(dist < bound)[0].astype(np.int64)
 
 
+def block_rows(tree: ClusterTree, eta: float, clusters, diam: np.ndarray | None = None,
+               chunk: int = 256) -> dict:
+    """block_row for each listed cluster, evaluated for `chunk` clusters at a time with
+    the same operations in the same order (an (chunk x n_clusters) array per step)."""
+    if diam is None:
+        diam = diameters(tree)
+    cl = np.unique(np.asarray(clusters, dtype=np.int64))
+    out = {}
+    for s in range(0, len(cl), chunk):
+        c = cl[s:s + chunk]
+        gap = np.maximum(0.0, np.maximum(tree.lo[None, :, :] - tree.hi[c][:, None, :],
+                                         tree.lo[c][:, None, :] - tree.hi[None, :, :]))
+        dist = _norm_rows(gap)
+        bound = eta * np.maximum(diam[c][:, None], diam[None, :])
+        keep = dist < bound
+        for t, cc in enumerate(c):
+            out[int(cc)] = np.nonzero(keep[t])[0].astype(np.int64)
+    return out
+
+
 def block_pattern(tree: ClusterTree, eta: float) -> list[np.ndarray]:
     """For each cluster nu, the sorted array of clusters nu' with (nu, nu') kept.
 

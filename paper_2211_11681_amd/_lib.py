@@ -23,6 +23,11 @@ SIGNATURES = {
     "spm_tree_block_pattern": [_P, _D, _P, _P, _P],
     "spm_compress_pattern_upload": [_I64, _P, _P, _I32, _P, _P, _P],
     "spm_block_pattern_upload": [_I64, _I32, _P, _P, _P, _P, _P],
+    "spm_block_pattern_plan": [_I64, _I32, _P, _P, _P, _P],
+    "spm_compress_pattern_plan": [_I64, _P, _P, _I32, _P, _P],
+    "spm_pattern_workspace_bytes": [_P, _P],
+    "spm_pattern_upload_workspace": [_P, _P, ctypes.c_size_t, _P],
+    "spm_pattern_classes": [_P, _P, _P, _P, _P, _P, _P, _P],
     "spm_pattern_destroy": [_P],
     "spm_pattern_info": [_P, _P, _P, _P, _P],
     "spm_pattern_tiles": [_P, _P, _P, _P],
@@ -31,7 +36,11 @@ SIGNATURES = {
     "spm_values_to_csr": [_P, _P, _P, _P],
     "spm_kernel_compress": [_P, _P, _I32, _D, _D, _I32, _P, _P],
     "spm_masked_gemm": [_P, _INT, _P, _INT, _P, _INT, _P, _P],
+    "spm_masked_gemm_workspace": [_P, _INT, _INT, _INT, _P],
+    "spm_masked_gemm_ws": [_P, _INT, _P, _INT, _P, _INT, _P, _P, ctypes.c_size_t, _P],
     "spm_masked_gemm_backward": [_P, _INT, _P, _P, _P, _P, _P, _P],
+    "spm_masked_gemm_backward_workspace": [_P, _INT, _P],
+    "spm_masked_gemm_backward_ws": [_P, _INT, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
     "spm_axpy": [_P, _INT, _D, _P, _D, _P, _P],
     "spm_convert": [_P, _INT, _P, _INT, _P, _P],
     "spm_sqdist": [_P, _INT, _P, _P, _P, _P],

@@ -243,6 +243,7 @@ extern "C" int spm_kernel_compress(spm_pattern p, spm_tree t, int32_t mp, double
                                    double *vals, void *stream)
 {
     if (!p || !t || !vals) return fail(SPM_EINVAL, "spm_kernel_compress: null pointer");
+    SPM_NEED_DEVICE(p, "spm_kernel_compress");
     if (mp < 0 || mp > 3 || !(ell > 0.0)) return fail(SPM_EINVAL, "spm_kernel_compress: bad kernel parameters");
     if (p->n != t->n || p->nc != t->nc || p->cstart != t->cstart)
         return fail(SPM_EINVAL, "spm_kernel_compress: pattern was not built on this tree's clusters");

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "spm_internal.h"
 
@@ -16,93 +17,102 @@ using spm::fail;
 
 namespace spm {
 
-template <typename T>
-static int to_device(DevBuf<T> &b, const std::vector<T> &v, hipStream_t s)
-{
-    b.n = v.size();
-    if (v.empty()) { b.ptr = nullptr; return SPM_OK; }
-    if (hipMalloc(&b.ptr, v.size() * sizeof(T)) != hipSuccess) {
-        b.ptr = nullptr;
-        return fail(SPM_ENOMEM, "device allocation for pattern layout");
-    }
-    // blocking copy: several sources are temporaries of the caller
-    (void)s;
-    SPM_HIP(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return SPM_OK;
-}
-
-template <typename T>
-static void release(DevBuf<T> &b)
-{
-    if (b.ptr) (void)hipFree(b.ptr);
-    b.ptr = nullptr;
-    b.n = 0;
-}
-
 static constexpr int kRedTiles = 64;      // tiles per reduction block
 static constexpr int kRedThreads = 256;
+static constexpr size_t kTableAlign = 256;
 
-int upload_pattern_device(spm_pattern_s *p, hipStream_t s)
+namespace {
+
+inline size_t align_up(size_t x) { return (x + kTableAlign - 1) & ~(kTableAlign - 1); }
+
+// Visits every device table of the pattern with its host source: f(device buffer, host
+// vector).  The keep mask and the reduction partials have no host vector; they are
+// handled by the callers.
+template <class F>
+void for_each_table(spm_pattern_s *p, F &&f)
 {
-    int st;
-    if ((st = to_device(p->d_cstart, p->cstart, s))) return st;
-    if ((st = to_device(p->d_blk_rp, p->blk_rp, s))) return st;
-    if ((st = to_device(p->d_tile_off, p->tile_off, s))) return st;
-    if ((st = to_device(p->d_colprefix, p->colprefix, s))) return st;
-    if ((st = to_device(p->d_rowbase, p->rowbase, s))) return st;
-    if ((st = to_device(p->d_rowlen, p->rowlen, s))) return st;
-    if ((st = to_device(p->d_pc_rp, p->pc_rp, s))) return st;
-    if ((st = to_device(p->d_pc_off, p->pc_off, s))) return st;
-    if ((st = to_device(p->d_pc_g, p->pc_g, s))) return st;
-    if ((st = to_device(p->d_pc_w, p->pc_w, s))) return st;
-    if ((st = to_device(p->d_nfun, p->nfun, s))) return st;
-    if ((st = to_device(p->d_tile_row, p->tile_row, s))) return st;
-    if ((st = to_device(p->d_tile_col, p->tile_col, s))) return st;
-    if ((st = to_device(p->d_trans, p->trans, s))) return st;
-    if ((st = to_device(p->d_diag_tile, p->diag_tile, s))) return st;
-    if ((st = to_device(p->d_order, p->order, s))) return st;
-    if ((st = to_device(p->d_grp_mem, p->grp_mem, s))) return st;
-    if ((st = to_device(p->d_grp_s, p->grp_s, s))) return st;
-    if ((st = to_device(p->d_grp_g, p->grp_g, s))) return st;
-    if ((st = to_device(p->d_grp_R, p->grp_R, s))) return st;
-    if ((st = to_device(p->d_gl_rp, p->gl_rp, s))) return st;
-    if ((st = to_device(p->d_gl_mu, p->gl_mu, s))) return st;
-    if ((st = to_device(p->d_gl_tile, p->gl_tile, s))) return st;
-    if ((st = to_device(p->d_unit_gr, p->unit_gr, s))) return st;
-    if ((st = to_device(p->d_unit_gc, p->unit_gc, s))) return st;
-    if ((st = to_device(p->d_unit_out, p->unit_out, s))) return st;
-    if ((st = to_device(p->d_unit_order, p->unit_order, s))) return st;
-    if ((st = to_device(p->d_pair_off, p->pair_off, s))) return st;
-    if ((st = to_device(p->d_pair_a, p->pair_a, s))) return st;
-    if ((st = to_device(p->d_pair_b, p->pair_b, s))) return st;
-    if ((st = to_device(p->d_gl_nm, p->gl_nm, s))) return st;
-    if ((st = to_device(p->d_gl_offd, p->gl_offd, s))) return st;
-    if ((st = to_device(p->d_stage_off, p->stage_off, s))) return st;
-    if ((st = to_device(p->d_stage_first, p->stage_first, s))) return st;
-    if (!p->csr_pos.empty()) {
-        if ((st = to_device(p->d_csr_pos, p->csr_pos, s))) return st;
+    f(p->d_cstart, p->cstart); f(p->d_blk_rp, p->blk_rp); f(p->d_tile_off, p->tile_off);
+    f(p->d_colprefix, p->colprefix); f(p->d_rowbase, p->rowbase); f(p->d_rowlen, p->rowlen);
+    f(p->d_pc_rp, p->pc_rp); f(p->d_pc_off, p->pc_off); f(p->d_pc_g, p->pc_g); f(p->d_pc_w, p->pc_w);
+    f(p->d_nfun, p->nfun); f(p->d_tile_row, p->tile_row); f(p->d_tile_col, p->tile_col);
+    f(p->d_trans, p->trans); f(p->d_diag_tile, p->diag_tile); f(p->d_order, p->order);
+    f(p->d_grp_mem, p->grp_mem); f(p->d_grp_s, p->grp_s); f(p->d_grp_g, p->grp_g); f(p->d_grp_R, p->grp_R);
+    f(p->d_gl_rp, p->gl_rp); f(p->d_gl_mu, p->gl_mu); f(p->d_gl_tile, p->gl_tile);
+    f(p->d_unit_gr, p->unit_gr); f(p->d_unit_gc, p->unit_gc); f(p->d_unit_out, p->unit_out);
+    f(p->d_unit_order, p->unit_order); f(p->d_pair_off, p->pair_off); f(p->d_pair_a, p->pair_a);
+    f(p->d_pair_b, p->pair_b); f(p->d_gl_nm, p->gl_nm); f(p->d_gl_offd, p->gl_offd);
+    f(p->d_stage_off, p->stage_off); f(p->d_stage_first, p->stage_first); f(p->d_csr_pos, p->csr_pos);
+}
+
+int64_t partial_count(const spm_pattern_s *p) { return (p->n_tiles + kRedTiles - 1) / kRedTiles + 1; }
+
+}  // namespace
+
+size_t pattern_device_bytes(const spm_pattern_s *pc)
+{
+    spm_pattern_s *p = const_cast<spm_pattern_s *>(pc);
+    size_t b = 0;
+    for_each_table(p, [&](auto &, const auto &v) { b += align_up(v.size() * sizeof(v[0])); });
+    if (p->masked) b += align_up((size_t)p->n_stored);
+    b += align_up((size_t)partial_count(p) * sizeof(double));
+    return b;
+}
+
+int upload_pattern_device(spm_pattern_s *p, void *ws, size_t bytes, hipStream_t s)
+{
+    (void)s;
+    const size_t need = pattern_device_bytes(p);
+    if (ws) {
+        if (bytes < need) return fail(SPM_EINVAL, "pattern upload: workspace too small");
+        if (reinterpret_cast<uintptr_t>(ws) % kTableAlign)
+            return fail(SPM_EINVAL, "pattern upload: workspace not aligned to 256 bytes");
+        p->dev_block = ws;
+        p->owns_block = false;
+    } else {
+        if (hipMalloc(&p->dev_block, need) != hipSuccess) {
+            p->dev_block = nullptr;
+            return fail(SPM_ENOMEM, "device allocation for the pattern layout");
+        }
+        p->owns_block = true;
+    }
+    char *base = static_cast<char *>(p->dev_block);
+    size_t off = 0;
+    int st = SPM_OK;
+    // blocking copies: the host tables may be modified or freed by the caller afterwards
+    for_each_table(p, [&](auto &d, const auto &v) {
+        using T = std::remove_reference_t<decltype(v[0])>;
+        d.n = v.size();
+        d.ptr = v.empty() ? nullptr : reinterpret_cast<std::remove_const_t<T> *>(base + off);
+        if (!st && !v.empty() && hipMemcpy(d.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(SPM_EHIP, "pattern upload: hipMemcpy failed");
+        off += align_up(v.size() * sizeof(T));
+    });
+    if (st) return st;
+    if (p->masked) {
         std::vector<uint8_t> keep(p->n_stored);
         for (int64_t e = 0; e < p->n_stored; ++e) keep[e] = p->csr_pos[e] >= 0;
-        if (p->masked && (st = to_device(p->d_keep, keep, s))) return st;
+        p->d_keep.ptr = reinterpret_cast<uint8_t *>(base + off);
+        p->d_keep.n = keep.size();
+        SPM_HIP(hipMemcpy(p->d_keep.ptr, keep.data(), keep.size(), hipMemcpyHostToDevice));
+        off += align_up((size_t)p->n_stored);
     }
-    int64_t nblk = (p->n_tiles + kRedTiles - 1) / kRedTiles + 1;
-    std::vector<double> zeros(nblk, 0.0);
-    if ((st = to_device(p->d_partial, zeros, s))) return st;
-    SPM_HIP(hipStreamSynchronize(s));
+    std::vector<double> zeros(partial_count(p), 0.0);
+    p->d_partial.ptr = reinterpret_cast<double *>(base + off);
+    p->d_partial.n = zeros.size();
+    SPM_HIP(hipMemcpy(p->d_partial.ptr, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice));
+    p->uploaded = true;
     return SPM_OK;
 }
 
 void free_pattern_device(spm_pattern_s *p)
 {
-    release(p->d_cstart); release(p->d_blk_rp); release(p->d_tile_off); release(p->d_colprefix);
-    release(p->d_rowbase); release(p->d_rowlen); release(p->d_csr_pos);
-    release(p->d_pc_rp); release(p->d_pc_off); release(p->d_pc_g); release(p->d_pc_w);
-    release(p->d_nfun); release(p->d_tile_row); release(p->d_tile_col); release(p->d_trans);
-    release(p->d_diag_tile); release(p->d_order); release(p->d_keep); release(p->d_partial);
-    release(p->d_grp_mem); release(p->d_grp_s); release(p->d_grp_g); release(p->d_grp_R); release(p->d_gl_rp);
-    release(p->d_gl_mu); release(p->d_gl_tile); release(p->d_unit_gr); release(p->d_unit_gc); release(p->d_unit_out);
-    release(p->d_unit_order); release(p->d_pair_off); release(p->d_pair_a); release(p->d_pair_b);
-    release(p->d_gl_nm); release(p->d_gl_offd); release(p->d_stage_off); release(p->d_stage_first);
+    if (p->owns_block && p->dev_block) (void)hipFree(p->dev_block);
+    p->dev_block = nullptr;
+    p->owns_block = false;
+    p->uploaded = false;
+    for_each_table(p, [&](auto &d, const auto &) { d.ptr = nullptr; d.n = 0; });
+    p->d_keep = {};
+    p->d_partial = {};
 }
 
 }  // namespace spm
@@ -1952,42 +1962,52 @@ int launch_transpose(spm_pattern p, const T *in, T *out, hipStream_t s)
     return SPM_OK;
 }
 
-// C = P_S(op(A) op(B)): the grouped kernel computes P_S(A' B'^T) with A' = op(A) and
-// B'^T = op(B), so A is transposed when op(A) = A^T and B when op(B) = B.  The
-// transposed copies live in stream-ordered temporary device memory.
-int launch_gemm_grouped(spm_pattern p, const double *A, int ta, const double *B, int tb, double *C, hipStream_t s)
+size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// F32ACC runs on the register-direct FP32 kernel when every unit class has at most 7 x 7
+// blocks, else on the per-tile kernel.
+bool f32acc_grouped(spm_pattern p)
 {
-    const size_t bytes = (size_t)p->n_stored * sizeof(double);
-    double *ta_buf = nullptr, *tb_buf = nullptr;
-    if (ta) SPM_HIP(hipMallocAsync((void **)&ta_buf, bytes, s));
-    if (!tb) {
-        if (hipMallocAsync((void **)&tb_buf, bytes, s) != hipSuccess) {
-            if (ta_buf) (void)hipFreeAsync(ta_buf, s);
-            return fail(SPM_ENOMEM, "masked product: temporary transpose buffer");
-        }
-    }
+    for (const auto &L : p->launches)
+        if (L.rb > 7 || L.cb > 7) return false;
+    return true;
+}
+
+// Workspace of one product C = P_S(op(A) op(B)): the grouped kernels compute
+// P_S(A' B'^T) with A' = op(A) and B'^T = op(B), so A is transposed into the
+// workspace when op(A) = A^T and B when op(B) = B.
+size_t gemm_ws_bytes(spm_pattern p, int prec, int ta, int tb)
+{
+    if (p->n_tiles == 0) return 0;
+    size_t el;
+    if (prec == SPM_F64) el = sizeof(double);
+    else if (prec == SPM_F32ACC && f32acc_grouped(p)) el = sizeof(float);
+    else return 0;                                   // per-tile kernel: reads both operands in place
+    const size_t vb = ws_align((size_t)p->n_stored * el);
+    return (ta ? vb : 0) + (tb ? 0 : vb);
+}
+
+// C = P_S(op(A) op(B)) with the grouped FP64 kernels; the transposed copies go to ws.
+int gemm_grouped_ws(spm_pattern p, const double *A, int ta, const double *B, int tb, double *C, char *ws,
+                    hipStream_t s)
+{
+    const size_t vb = ws_align((size_t)p->n_stored * sizeof(double));
+    double *ta_buf = ta ? reinterpret_cast<double *>(ws) : nullptr;
+    double *tb_buf = tb ? nullptr : reinterpret_cast<double *>(ws + (ta ? vb : 0));
     int st = SPM_OK;
     if (ta) st = launch_transpose(p, A, ta_buf, s);
     if (!st && !tb) st = launch_transpose(p, B, tb_buf, s);
     if (!st) st = launch_gemm_abt(p, ta ? ta_buf : A, tb ? B : tb_buf, C, s);
-    if (ta_buf) (void)hipFreeAsync(ta_buf, s);
-    if (tb_buf) (void)hipFreeAsync(tb_buf, s);
     return st;
 }
 
 // F32ACC: C = P_S(op(A) op(B)) with the register-direct FP32 kernel (unit classes of at
-// most 7 x 7 blocks; returns SPM_EUNSUPPORTED, before launching anything, otherwise).
-int launch_gemm_f32acc(spm_pattern p, const float *A, int ta, const float *B, int tb, float *C, hipStream_t s)
+// most 7 x 7 blocks).
+int gemm_f32acc_ws(spm_pattern p, const float *A, int ta, const float *B, int tb, float *C, char *ws, hipStream_t s)
 {
-    for (const auto &L : p->launches)
-        if (L.rb > 7 || L.cb > 7) return SPM_EUNSUPPORTED;
-    const size_t bytes = (size_t)p->n_stored * sizeof(float);
-    float *ta_buf = nullptr, *tb_buf = nullptr;
-    if (ta) SPM_HIP(hipMallocAsync((void **)&ta_buf, bytes, s));
-    if (!tb && hipMallocAsync((void **)&tb_buf, bytes, s) != hipSuccess) {
-        if (ta_buf) (void)hipFreeAsync(ta_buf, s);
-        return fail(SPM_ENOMEM, "masked product: temporary transpose buffer");
-    }
+    const size_t vb = ws_align((size_t)p->n_stored * sizeof(float));
+    float *ta_buf = ta ? reinterpret_cast<float *>(ws) : nullptr;
+    float *tb_buf = tb ? nullptr : reinterpret_cast<float *>(ws + (ta ? vb : 0));
     int st = SPM_OK;
     if (ta) st = launch_transpose(p, A, ta_buf, s);
     if (!st && !tb) st = launch_transpose(p, B, tb_buf, s);
@@ -2031,40 +2051,27 @@ int launch_gemm_f32acc(spm_pattern p, const float *A, int ta, const float *B, in
         st = launch_grp(k, grid, threads, ring, s, g, reinterpret_cast<const double *>(Ap),
                         reinterpret_cast<const double *>(Bp), reinterpret_cast<double *>(C));
     }
-    if (ta_buf) (void)hipFreeAsync(ta_buf, s);
-    if (tb_buf) (void)hipFreeAsync(tb_buf, s);
     return st;
 }
 
-int launch_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C, hipStream_t s)
+// C = P_S(op(A) op(B)) in precision prec with a workspace of at least
+// gemm_ws_bytes(p, prec, ta, tb) bytes (256-byte aligned).
+int gemm_ws(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C, void *ws,
+            hipStream_t s)
 {
     if (p->n_tiles == 0) return SPM_OK;
-    if (prec == SPM_F32ACC) {
-        int st = launch_gemm_f32acc(p, static_cast<const float *>(A), ta, static_cast<const float *>(B), tb,
-                                    static_cast<float *>(C), s);
-        if (st == SPM_OK) {
-            if (p->d_keep.ptr)
-                hipLaunchKernelGGL(k_apply_keep, dim3(grid1d(p->n_stored, 256)), dim3(256), 0, s, p->n_stored, prec,
-                                   p->d_keep.ptr, C);
-            SPM_HIP(hipGetLastError());
-            return SPM_OK;
-        }
-        if (st != SPM_EUNSUPPORTED) return st;       // classes wider than 7 blocks: per-tile kernel below
-    }
+    char *w = static_cast<char *>(ws);
+    int st;
     if (prec == SPM_F64) {
-        int st = launch_gemm_grouped(p, static_cast<const double *>(A), ta, static_cast<const double *>(B), tb,
-                                     static_cast<double *>(C), s);
-        if (st) return st;
-        if (p->d_keep.ptr)
-            hipLaunchKernelGGL(k_apply_keep, dim3(grid1d(p->n_stored, 256)), dim3(256), 0, s, p->n_stored, prec,
-                               p->d_keep.ptr, C);
-        SPM_HIP(hipGetLastError());
-        return SPM_OK;
-    }
-    GemmArgs g = gemm_args(p);
-    dim3 grid((unsigned)p->n_tiles), block(64);
-    const int sel = (ta ? 2 : 0) + (tb ? 1 : 0);
-    {
+        st = gemm_grouped_ws(p, static_cast<const double *>(A), ta, static_cast<const double *>(B), tb,
+                             static_cast<double *>(C), w, s);
+    } else if (prec == SPM_F32ACC && f32acc_grouped(p)) {
+        st = gemm_f32acc_ws(p, static_cast<const float *>(A), ta, static_cast<const float *>(B), tb,
+                            static_cast<float *>(C), w, s);
+    } else {
+        GemmArgs g = gemm_args(p);
+        dim3 grid((unsigned)p->n_tiles), block(64);
+        const int sel = (ta ? 2 : 0) + (tb ? 1 : 0);
         auto a = static_cast<const float *>(A);
         auto b = static_cast<const float *>(B);
         auto c = static_cast<float *>(C);
@@ -2079,12 +2086,26 @@ int launch_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, i
         case 6: hipLaunchKernelGGL((k_mgemm_f32<1, 0, true>), grid, block, 0, s, g, a, b, c); break;
         default: hipLaunchKernelGGL((k_mgemm_f32<1, 1, true>), grid, block, 0, s, g, a, b, c); break;
         }
+        st = SPM_OK;
     }
+    if (st) return st;
     if (p->d_keep.ptr)
         hipLaunchKernelGGL(k_apply_keep, dim3(grid1d(p->n_stored, 256)), dim3(256), 0, s, p->n_stored, prec,
                            p->d_keep.ptr, C);
     SPM_HIP(hipGetLastError());
     return SPM_OK;
+}
+
+// The same with a stream-ordered temporary workspace.
+int launch_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C, hipStream_t s)
+{
+    const size_t need = gemm_ws_bytes(p, prec, ta, tb);
+    void *ws = nullptr;
+    if (need && hipMallocAsync(&ws, need, s) != hipSuccess)
+        return fail(SPM_ENOMEM, "masked product: temporary workspace");
+    const int st = gemm_ws(p, prec, A, ta, B, tb, C, ws, s);
+    if (ws) (void)hipFreeAsync(ws, s);
+    return st;
 }
 
 int launch_reduce(spm_pattern p, int op, int prec, const void *x, const void *y, const double *vec, double alpha,
@@ -2127,6 +2148,7 @@ int launch_convert(spm_pattern p, int pf, const void *X, int pt, void *Y, hipStr
 extern "C" int spm_values_from_csr(spm_pattern p, const double *csr, double *vals, void *stream)
 {
     if (!p || !csr || !vals) return fail(SPM_EINVAL, "spm_values_from_csr: null pointer");
+    SPM_NEED_DEVICE(p, "spm_values_from_csr");
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_from_csr, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(64), 0, s, p->n_tiles,
                        p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_nfun.ptr, p->d_rowbase.ptr,
@@ -2138,6 +2160,7 @@ extern "C" int spm_values_from_csr(spm_pattern p, const double *csr, double *val
 extern "C" int spm_values_to_csr(spm_pattern p, const double *vals, double *csr, void *stream)
 {
     if (!p || !csr || !vals) return fail(SPM_EINVAL, "spm_values_to_csr: null pointer");
+    SPM_NEED_DEVICE(p, "spm_values_to_csr");
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_from_csr, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(64), 0, s, p->n_tiles,
                        p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_nfun.ptr, p->d_rowbase.ptr,
@@ -2146,36 +2169,113 @@ extern "C" int spm_values_to_csr(spm_pattern p, const double *vals, double *csr,
     return SPM_OK;
 }
 
+static int check_gemm_args(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, const void *C,
+                           const char *name)
+{
+    if (!p || !A || !B || !C) return fail(SPM_EINVAL, std::string(name) + ": null pointer");
+    SPM_NEED_DEVICE(p, name);
+    if (!valid_prec(prec)) return fail(SPM_EINVAL, std::string(name) + ": bad precision");
+    if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) return fail(SPM_EINVAL, std::string(name) + ": bad transpose flag");
+    const size_t vb = value_bytes(p, prec);
+    if (overlap(A, C, vb) || overlap(B, C, vb)) return fail(SPM_EINVAL, std::string(name) + ": C aliases an operand");
+    return SPM_OK;
+}
+
 extern "C" int spm_masked_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C,
                                void *stream)
 {
-    if (!p || !A || !B || !C) return fail(SPM_EINVAL, "spm_masked_gemm: null pointer");
-    if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_masked_gemm: bad precision");
-    if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) return fail(SPM_EINVAL, "spm_masked_gemm: bad transpose flag");
-    const size_t vb = value_bytes(p, prec);
-    if (overlap(A, C, vb) || overlap(B, C, vb)) return fail(SPM_EINVAL, "spm_masked_gemm: C aliases an operand");
+    int st = check_gemm_args(p, prec, A, ta, B, tb, C, "spm_masked_gemm");
+    if (st) return st;
     return spm::launch_gemm(p, prec, A, ta, B, tb, C, (hipStream_t)stream);
+}
+
+extern "C" int spm_masked_gemm_workspace(spm_pattern p, int prec, int ta, int tb, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPM_EINVAL, "spm_masked_gemm_workspace: null pointer");
+    if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_masked_gemm_workspace: bad precision");
+    *bytes = spm::gemm_ws_bytes(p, prec, ta != 0, tb != 0);
+    return SPM_OK;
+}
+
+// ws must not overlap A, B or C (the transposed operands are written there).
+static int check_ws(spm_pattern p, int prec, const void *const *bufs, int nbufs, const void *ws, size_t bytes,
+                    size_t need, const char *name)
+{
+    if (need == 0) return SPM_OK;
+    if (!ws || bytes < need) return fail(SPM_EINVAL, std::string(name) + ": workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SPM_EINVAL, std::string(name) + ": workspace not 256-byte aligned");
+    const size_t vb = value_bytes(p, prec);
+    for (int i = 0; i < nbufs; ++i)
+        if (overlap2(bufs[i], vb, ws, need)) return fail(SPM_EINVAL, std::string(name) + ": workspace overlaps an operand");
+    return SPM_OK;
+}
+
+extern "C" int spm_masked_gemm_ws(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C,
+                                  void *ws, size_t bytes, void *stream)
+{
+    int st = check_gemm_args(p, prec, A, ta, B, tb, C, "spm_masked_gemm_ws");
+    if (st) return st;
+    const void *bufs[3] = {A, B, C};
+    if ((st = check_ws(p, prec, bufs, 3, ws, bytes, spm::gemm_ws_bytes(p, prec, ta, tb), "spm_masked_gemm_ws")))
+        return st;
+    return spm::gemm_ws(p, prec, A, ta, B, tb, C, ws, (hipStream_t)stream);
+}
+
+static size_t backward_ws_bytes(spm_pattern p, int prec)
+{
+    return std::max(spm::gemm_ws_bytes(p, prec, 0, 1), spm::gemm_ws_bytes(p, prec, 1, 0));
+}
+
+static int check_backward(spm_pattern p, int prec, const void *dC, const void *A, const void *B, void *dA, void *dB,
+                          const char *name)
+{
+    if (!p || !dC || !A || !B) return fail(SPM_EINVAL, std::string(name) + ": null pointer");
+    SPM_NEED_DEVICE(p, name);
+    if (!valid_prec(prec)) return fail(SPM_EINVAL, std::string(name) + ": bad precision");
+    const size_t vb = value_bytes(p, prec);
+    for (void *o : {dA, dB})
+        if (o && (overlap(o, dC, vb) || overlap(o, A, vb) || overlap(o, B, vb)))
+            return fail(SPM_EINVAL, std::string(name) + ": output aliases an input");
+    if (dA && dB && overlap(dA, dB, vb)) return fail(SPM_EINVAL, std::string(name) + ": dA aliases dB");
+    return SPM_OK;
 }
 
 extern "C" int spm_masked_gemm_backward(spm_pattern p, int prec, const void *dC, const void *A, const void *B,
                                         void *dA, void *dB, void *stream)
 {
-    if (!p || !dC || !A || !B) return fail(SPM_EINVAL, "spm_masked_gemm_backward: null pointer");
-    if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_masked_gemm_backward: bad precision");
-    const size_t vb = value_bytes(p, prec);
-    for (void *o : {dA, dB})
-        if (o && (overlap(o, dC, vb) || overlap(o, A, vb) || overlap(o, B, vb)))
-            return fail(SPM_EINVAL, "spm_masked_gemm_backward: output aliases an input");
-    if (dA && dB && overlap(dA, dB, vb)) return fail(SPM_EINVAL, "spm_masked_gemm_backward: dA aliases dB");
-    int st;
+    int st = check_backward(p, prec, dC, A, B, dA, dB, "spm_masked_gemm_backward");
+    if (st) return st;
     if (dA && (st = spm::launch_gemm(p, prec, dC, 0, B, 1, dA, (hipStream_t)stream))) return st;   // P_S(dC B^T)
     if (dB && (st = spm::launch_gemm(p, prec, A, 1, dC, 0, dB, (hipStream_t)stream))) return st;   // P_S(A^T dC)
+    return SPM_OK;
+}
+
+extern "C" int spm_masked_gemm_backward_workspace(spm_pattern p, int prec, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPM_EINVAL, "spm_masked_gemm_backward_workspace: null pointer");
+    if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_masked_gemm_backward_workspace: bad precision");
+    *bytes = backward_ws_bytes(p, prec);
+    return SPM_OK;
+}
+
+extern "C" int spm_masked_gemm_backward_ws(spm_pattern p, int prec, const void *dC, const void *A, const void *B,
+                                           void *dA, void *dB, void *ws, size_t bytes, void *stream)
+{
+    int st = check_backward(p, prec, dC, A, B, dA, dB, "spm_masked_gemm_backward_ws");
+    if (st) return st;
+    const void *bufs[5] = {dC, A, B, dA, dB};
+    if ((st = check_ws(p, prec, bufs, 5, ws, bytes, backward_ws_bytes(p, prec), "spm_masked_gemm_backward_ws")))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (dA && (st = spm::gemm_ws(p, prec, dC, 0, B, 1, dA, ws, s))) return st;   // P_S(dC B^T)
+    if (dB && (st = spm::gemm_ws(p, prec, A, 1, dC, 0, dB, ws, s))) return st;   // P_S(A^T dC)
     return SPM_OK;
 }
 
 extern "C" int spm_axpy(spm_pattern p, int prec, double alpha, const void *X, double beta, void *Y, void *stream)
 {
     if (!p || !Y) return fail(SPM_EINVAL, "spm_axpy: null pointer");
+    SPM_NEED_DEVICE(p, "spm_axpy");
     if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_axpy: bad precision");
     return spm::launch_axpy(p, prec, alpha, X, beta, Y, (hipStream_t)stream);
 }
@@ -2183,6 +2283,7 @@ extern "C" int spm_axpy(spm_pattern p, int prec, double alpha, const void *X, do
 extern "C" int spm_convert(spm_pattern p, int pf, const void *X, int pt, void *Y, void *stream)
 {
     if (!p || !X || !Y) return fail(SPM_EINVAL, "spm_convert: null pointer");
+    SPM_NEED_DEVICE(p, "spm_convert");
     if (!valid_prec(pf) || !valid_prec(pt)) return fail(SPM_EINVAL, "spm_convert: bad precision");
     if (overlap2(X, value_bytes(p, pf), Y, value_bytes(p, pt)))
         return fail(SPM_EINVAL, "spm_convert: X and Y overlap");
@@ -2192,6 +2293,7 @@ extern "C" int spm_convert(spm_pattern p, int pf, const void *X, int pt, void *Y
 extern "C" int spm_sqdist(spm_pattern p, int prec, const void *X, const void *Y, double *out, void *stream)
 {
     if (!p || !X || !out) return fail(SPM_EINVAL, "spm_sqdist: null pointer");
+    SPM_NEED_DEVICE(p, "spm_sqdist");
     if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_sqdist: bad precision");
     return spm::launch_reduce(p, RED_SQDIST, prec, X, Y, nullptr, 0.0, 0, 1.0, out, (hipStream_t)stream);
 }
@@ -2199,6 +2301,7 @@ extern "C" int spm_sqdist(spm_pattern p, int prec, const void *X, const void *Y,
 extern "C" int spm_sqdist_eye(spm_pattern p, int prec, double alpha, const void *X, double *out, void *stream)
 {
     if (!p || !X || !out) return fail(SPM_EINVAL, "spm_sqdist_eye: null pointer");
+    SPM_NEED_DEVICE(p, "spm_sqdist_eye");
     if (!valid_prec(prec)) return fail(SPM_EINVAL, "spm_sqdist_eye: bad precision");
     return spm::launch_reduce(p, RED_SQDIST_EYE, prec, X, nullptr, nullptr, alpha, 0, 1.0, out, (hipStream_t)stream);
 }
@@ -2206,18 +2309,21 @@ extern "C" int spm_sqdist_eye(spm_pattern p, int prec, double alpha, const void 
 extern "C" int spm_dot(spm_pattern p, const double *X, const double *Y, double *out, void *stream)
 {
     if (!p || !X || !Y || !out) return fail(SPM_EINVAL, "spm_dot: null pointer");
+    SPM_NEED_DEVICE(p, "spm_dot");
     return spm::launch_reduce(p, RED_DOT, SPM_F64, X, Y, nullptr, 0.0, 0, 1.0, out, (hipStream_t)stream);
 }
 
 extern "C" int spm_quadform(spm_pattern p, const double *X, const double *y, double *out, void *stream)
 {
     if (!p || !X || !y || !out) return fail(SPM_EINVAL, "spm_quadform: null pointer");
+    SPM_NEED_DEVICE(p, "spm_quadform");
     return spm::launch_reduce(p, RED_QUAD, SPM_F64, X, nullptr, y, 0.0, 0, 1.0, out, (hipStream_t)stream);
 }
 
 extern "C" int spm_fill_outer(spm_pattern p, double alpha, const double *y, double *X, void *stream)
 {
     if (!p || !y || !X) return fail(SPM_EINVAL, "spm_fill_outer: null pointer");
+    SPM_NEED_DEVICE(p, "spm_fill_outer");
     hipLaunchKernelGGL(k_fill_outer, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(64), 0, (hipStream_t)stream,
                        p->n_tiles, p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_nfun.ptr,
                        p->d_cstart.ptr, p->d_keep.ptr, alpha, y, X);
@@ -2234,11 +2340,18 @@ __global__ void k_fill(int64_t ns, int prec, double v, void *x)
         store_val(prec, x, e, ns, v);
 }
 
+// Newton-Schulz scratch: Y and T (FP64), the bulk-precision copies of A, X, Y, T, and
+// the workspace of one product, each 256-byte aligned.
+// Newton-Schulz scratch: Y and T (FP64), then a region used by the bulk iterations for
+// the bulk-precision copies of A, X, Y, T and their product workspace, and afterwards
+// by the FP64 iterations for theirs.  Every part is 256-byte aligned.
 size_t ns_scratch(spm_pattern p, int bulk, int32_t nbulk)
 {
-    size_t b = 2 * (size_t)p->n_stored * sizeof(double);
-    if (bulk != SPM_F64 && nbulk > 0) b += 4 * value_bytes(p, bulk);
-    return b;
+    const size_t vb8 = spm::ws_align((size_t)p->n_stored * sizeof(double));
+    size_t region = spm::gemm_ws_bytes(p, SPM_F64, 0, 0);
+    if (bulk != SPM_F64 && nbulk > 0)
+        region = std::max(region, 4 * spm::ws_align(value_bytes(p, bulk)) + spm::gemm_ws_bytes(p, bulk, 0, 0));
+    return 2 * vb8 + region;
 }
 
 }  // namespace
@@ -2246,7 +2359,7 @@ size_t ns_scratch(spm_pattern p, int bulk, int32_t nbulk)
 extern "C" int spm_expm_taylor_scratch(spm_pattern p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPM_EINVAL, "spm_expm_taylor_scratch: null pointer");
-    *bytes = (size_t)p->n_stored * sizeof(double);
+    *bytes = spm::ws_align((size_t)p->n_stored * sizeof(double)) + spm::gemm_ws_bytes(p, SPM_F64, 0, 0);
     return SPM_OK;
 }
 
@@ -2258,19 +2371,24 @@ extern "C" int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_
                                size_t scratch_bytes, void *stream)
 {
     if (!p || !A || !E) return fail(SPM_EINVAL, "spm_expm_taylor: null pointer");
+    SPM_NEED_DEVICE(p, "spm_expm_taylor");
     if (terms < 0) return fail(SPM_EINVAL, "spm_expm_taylor: negative number of terms");
-    const size_t vb8 = (size_t)p->n_stored * sizeof(double);
-    if (terms > 0 && (!scratch || scratch_bytes < vb8)) return fail(SPM_EINVAL, "spm_expm_taylor: scratch too small");
-    if (overlap(A, E, vb8) || (terms > 0 && (overlap2(A, vb8, scratch, vb8) || overlap2(E, vb8, scratch, vb8))))
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), vba = spm::ws_align(vb8);
+    const size_t need = vba + spm::gemm_ws_bytes(p, SPM_F64, 0, 0);
+    if (terms > 0 && (!scratch || scratch_bytes < need)) return fail(SPM_EINVAL, "spm_expm_taylor: scratch too small");
+    if (terms > 0 && reinterpret_cast<uintptr_t>(scratch) % 256)
+        return fail(SPM_EINVAL, "spm_expm_taylor: scratch not 256-byte aligned");
+    if (overlap(A, E, vb8) || (terms > 0 && (overlap2(A, vb8, scratch, need) || overlap2(E, vb8, scratch, need))))
         return fail(SPM_EINVAL, "spm_expm_taylor: buffers overlap");
     hipStream_t s = (hipStream_t)stream;
     const int64_t ns = p->n_stored;
     double *cur = E, *oth = static_cast<double *>(scratch);
+    void *gw = static_cast<char *>(scratch) + vba;
     int st;
     hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)cur);
     if ((st = spm::launch_axpy(p, SPM_F64, 1.0, nullptr, 1.0, cur, s))) return st;
     for (int32_t k = terms; k >= 1; --k) {
-        if ((st = spm::launch_gemm(p, SPM_F64, A, 0, cur, 0, oth, s))) return st;
+        if ((st = spm::gemm_ws(p, SPM_F64, A, 0, cur, 0, oth, gw, s))) return st;
         if ((st = spm::launch_axpy(p, SPM_F64, 1.0, nullptr, 1.0 / k, oth, s))) return st;   // oth/k + I
         std::swap(cur, oth);
     }
@@ -2281,6 +2399,7 @@ extern "C" int spm_expm_taylor(spm_pattern p, const double *A, double *E, int32_
 extern "C" int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t r, double *Y, void *stream)
 {
     if (!p) return fail(SPM_EINVAL, "spm_spmm: null pattern");
+    SPM_NEED_DEVICE(p, "spm_spmm");
     if (r < 0) return fail(SPM_EINVAL, "spm_spmm: negative column count");
     if (r == 0 || p->nc == 0) return SPM_OK;                 // X and Y may then be null
     if (!A || !X || !Y) return fail(SPM_EINVAL, "spm_spmm: null pointer");
@@ -2299,7 +2418,7 @@ extern "C" int spm_spmm(spm_pattern p, const double *A, const double *X, int32_t
 extern "C" int spm_ns_sqrt_scratch(spm_pattern p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPM_EINVAL, "spm_ns_sqrt_scratch: null pointer");
-    *bytes = 3 * (size_t)p->n_stored * sizeof(double);
+    *bytes = 3 * spm::ws_align((size_t)p->n_stored * sizeof(double)) + spm::gemm_ws_bytes(p, SPM_F64, 0, 0);
     return SPM_OK;
 }
 
@@ -2312,29 +2431,34 @@ extern "C" int spm_ns_sqrt(spm_pattern p, const double *A, double *Y, double *Z,
                            double *residuals, void *scratch, size_t scratch_bytes, void *stream)
 {
     if (!p || !A || !Y || !Z) return fail(SPM_EINVAL, "spm_ns_sqrt: null pointer");
+    SPM_NEED_DEVICE(p, "spm_ns_sqrt");
     if (iters < 0) return fail(SPM_EINVAL, "spm_ns_sqrt: negative iteration count");
-    const size_t vb8 = (size_t)p->n_stored * sizeof(double), need = 3 * vb8;
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), vba = spm::ws_align(vb8);
+    const size_t need = 3 * vba + spm::gemm_ws_bytes(p, SPM_F64, 0, 0);
     if (!scratch || scratch_bytes < need) return fail(SPM_EINVAL, "spm_ns_sqrt: scratch too small");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(SPM_EINVAL, "spm_ns_sqrt: scratch not 256-byte aligned");
     if (overlap(A, Y, vb8) || overlap(A, Z, vb8) || overlap(Y, Z, vb8) || overlap2(A, vb8, scratch, need) ||
         overlap2(Y, vb8, scratch, need) || overlap2(Z, vb8, scratch, need))
         return fail(SPM_EINVAL, "spm_ns_sqrt: buffers overlap");
     hipStream_t s = (hipStream_t)stream;
     const int64_t ns = p->n_stored;
     const double rs = 1.0 / std::sqrt((double)p->n);
-    double *W = static_cast<double *>(scratch);
-    double *y = Y, *z = Z, *yn = W + ns, *zn = yn + ns;
+    char *sc = static_cast<char *>(scratch);
+    double *W = reinterpret_cast<double *>(sc);
+    double *y = Y, *z = Z, *yn = reinterpret_cast<double *>(sc + vba), *zn = reinterpret_cast<double *>(sc + 2 * vba);
+    void *gw = sc + 3 * vba;
     int st;
     SPM_HIP(hipMemcpyAsync(y, A, vb8, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)z);
     if ((st = spm::launch_axpy(p, SPM_F64, 1.0, nullptr, 1.0, z, s))) return st;
     for (int32_t k = 0; k < iters; ++k) {
-        if ((st = spm::launch_gemm(p, SPM_F64, z, 0, y, 0, W, s))) return st;          // P_S(Z Y)
+        if ((st = spm::gemm_ws(p, SPM_F64, z, 0, y, 0, W, gw, s))) return st;          // P_S(Z Y)
         if (residuals &&
             (st = spm::launch_reduce(p, 1, SPM_F64, W, nullptr, nullptr, 1.0, 1, rs, residuals + k, s)))
             return st;
         if ((st = spm::launch_axpy(p, SPM_F64, 1.5, nullptr, -0.5, W, s))) return st;  // T = (3I - W) / 2
-        if ((st = spm::launch_gemm(p, SPM_F64, y, 0, W, 0, yn, s))) return st;
-        if ((st = spm::launch_gemm(p, SPM_F64, W, 0, z, 0, zn, s))) return st;
+        if ((st = spm::gemm_ws(p, SPM_F64, y, 0, W, 0, yn, gw, s))) return st;
+        if ((st = spm::gemm_ws(p, SPM_F64, W, 0, z, 0, zn, gw, s))) return st;
         std::swap(y, yn);
         std::swap(z, zn);
     }
@@ -2356,22 +2480,29 @@ extern "C" int spm_newton_schulz(spm_pattern p, const double *A, double *X, int3
                                  size_t scratch_bytes, void *stream)
 {
     if (!p || !A || !X || !res) return fail(SPM_EINVAL, "spm_newton_schulz: null pointer");
+    SPM_NEED_DEVICE(p, "spm_newton_schulz");
     if (iters < 0 || nfin < 0) return fail(SPM_EINVAL, "spm_newton_schulz: negative iteration count");
     if (!valid_prec(bulk)) return fail(SPM_EINVAL, "spm_newton_schulz: bad precision");
     const int32_t nbulk = bulk == SPM_F64 ? 0 : std::max(0, iters - nfin);
     const size_t need = ns_scratch(p, bulk, nbulk);
     if (!scratch || scratch_bytes < need) return fail(SPM_EINVAL, "spm_newton_schulz: scratch too small");
-    const size_t vb8 = (size_t)p->n_stored * sizeof(double);
+    if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(SPM_EINVAL, "spm_newton_schulz: scratch not 256-byte aligned");
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), vba = spm::ws_align(vb8);
     if (overlap(A, X, vb8) || overlap2(X, vb8, scratch, need) || overlap2(A, vb8, scratch, need))
         return fail(SPM_EINVAL, "spm_newton_schulz: buffers overlap");
     hipStream_t s = (hipStream_t)stream;
     const int64_t ns = p->n_stored;
     const double rs = 1.0 / std::sqrt((double)p->n);
-    double *Y = static_cast<double *>(scratch);
-    double *T = Y + ns;
-    char *sp = reinterpret_cast<char *>(T + ns);
-    const size_t vb = value_bytes(p, bulk);
+    char *sc = static_cast<char *>(scratch);
+    double *Y = reinterpret_cast<double *>(sc);
+    double *T = reinterpret_cast<double *>(sc + vba);
+    char *sp = sc + 2 * vba;
+    const size_t vb = spm::ws_align(value_bytes(p, bulk));
+    const bool lowp = bulk != SPM_F64 && nbulk > 0;
     void *As = sp, *Xs = sp + vb, *Ys = sp + 2 * vb, *Ts = sp + 3 * vb;
+    void *gwb = sp + 4 * vb;                   // product workspace of the bulk iterations
+    void *gw = sp;                             // of the FP64 ones (the bulk copies are dead by then)
+    (void)lowp;
     double *cur = X, *oth = T;
     int st;
     hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)cur);
@@ -2387,28 +2518,32 @@ extern "C" int spm_newton_schulz(spm_pattern p, const double *A, double *X, int3
             else SPM_HIP(hipMemcpyAsync(ckpt[k], cur, vb8, hipMemcpyDeviceToDevice, s));
         }
         if (low) {
-            if ((st = spm::launch_gemm(p, bulk, As, 0, Xs, 0, Ys, s))) return st;
+            if ((st = spm::gemm_ws(p, bulk, As, 0, Xs, 0, Ys, gwb, s))) return st;
             if ((st = spm::launch_reduce(p, 1, bulk, Ys, nullptr, nullptr, 1.0, 1, rs, res + k, s))) return st;
             if ((st = spm::launch_axpy(p, bulk, 2.0, nullptr, -1.0, Ys, s))) return st;
-            if ((st = spm::launch_gemm(p, bulk, Xs, 0, Ys, 0, Ts, s))) return st;
+            if ((st = spm::gemm_ws(p, bulk, Xs, 0, Ys, 0, Ts, gwb, s))) return st;
             std::swap(Xs, Ts);
             if (k == nbulk - 1 && (st = spm::launch_convert(p, bulk, Xs, SPM_F64, cur, s))) return st;
         } else {
-            if ((st = spm::launch_gemm(p, SPM_F64, A, 0, cur, 0, Y, s))) return st;
+            if ((st = spm::gemm_ws(p, SPM_F64, A, 0, cur, 0, Y, gw, s))) return st;
             if ((st = spm::launch_reduce(p, 1, SPM_F64, Y, nullptr, nullptr, 1.0, 1, rs, res + k, s))) return st;
             if ((st = spm::launch_axpy(p, SPM_F64, 2.0, nullptr, -1.0, Y, s))) return st;
-            if ((st = spm::launch_gemm(p, SPM_F64, cur, 0, Y, 0, oth, s))) return st;
+            if ((st = spm::gemm_ws(p, SPM_F64, cur, 0, Y, 0, oth, gw, s))) return st;
             std::swap(cur, oth);
         }
     }
     if (ckpt && ckpt[iters]) SPM_HIP(hipMemcpyAsync(ckpt[iters], cur, vb8, hipMemcpyDeviceToDevice, s));
-    if ((st = spm::launch_gemm(p, SPM_F64, A, 0, cur, 0, Y, s))) return st;
+    if ((st = spm::gemm_ws(p, SPM_F64, A, 0, cur, 0, Y, gw, s))) return st;
     if ((st = spm::launch_reduce(p, 1, SPM_F64, Y, nullptr, nullptr, 1.0, 1, rs, res + iters, s))) return st;
     if (cur != X) SPM_HIP(hipMemcpyAsync(X, cur, vb8, hipMemcpyDeviceToDevice, s));
-    double last = 0.0;
+    double first = 0.0, last = 0.0;
+    SPM_HIP(hipMemcpyAsync(&first, res, sizeof(double), hipMemcpyDeviceToHost, s));
     SPM_HIP(hipMemcpyAsync(&last, res + iters, sizeof(double), hipMemcpyDeviceToHost, s));
     SPM_HIP(hipStreamSynchronize(s));
     if (!std::isfinite(last)) return fail(SPM_ENOTCONV, "spm_newton_schulz: residual is not finite");
+    if (last > first)
+        return fail(SPM_ENOTCONV, "spm_newton_schulz: final residual " + std::to_string(last) +
+                                      " exceeds the initial residual " + std::to_string(first));
     return SPM_OK;
 }
 
@@ -2417,7 +2552,8 @@ extern "C" int spm_contour_invsqrt_scratch(spm_pattern p, int32_t ns_iters, size
 {
     if (!p || !bytes) return fail(SPM_EINVAL, "spm_contour_invsqrt_scratch: null pointer");
     if (ns_iters < 0) return fail(SPM_EINVAL, "spm_contour_invsqrt_scratch: negative iteration count");
-    *bytes = 2 * (size_t)p->n_stored * sizeof(double) + ns_scratch(p, SPM_F64, 0) + (size_t)(ns_iters + 1) * sizeof(double);
+    *bytes = 2 * spm::ws_align((size_t)p->n_stored * sizeof(double)) + ns_scratch(p, SPM_F64, 0) +
+             (size_t)(ns_iters + 1) * sizeof(double);
     return SPM_OK;
 }
 
@@ -2428,19 +2564,22 @@ extern "C" int spm_contour_invsqrt(spm_pattern p, const double *A, double lam_mi
                                    size_t scratch_bytes, void *stream)
 {
     if (!p || !A || !out) return fail(SPM_EINVAL, "spm_contour_invsqrt: null pointer");
+    SPM_NEED_DEVICE(p, "spm_contour_invsqrt");
     if (ns_iters < 0) return fail(SPM_EINVAL, "spm_contour_invsqrt: negative iteration count");
     std::vector<double> w2(std::max(nodes, 1)), cw(std::max(nodes, 1));
     int st;
     if ((st = spm_contour_rule(lam_min, lam_max, nodes, w2.data(), cw.data()))) return st;
-    const size_t vb8 = (size_t)p->n_stored * sizeof(double), nsb = ns_scratch(p, SPM_F64, 0);
-    const size_t need = 2 * vb8 + nsb + (size_t)(ns_iters + 1) * sizeof(double);
+    const size_t vb8 = (size_t)p->n_stored * sizeof(double), vba = spm::ws_align(vb8), nsb = ns_scratch(p, SPM_F64, 0);
+    const size_t need = 2 * vba + nsb + (size_t)(ns_iters + 1) * sizeof(double);
     if (!scratch || scratch_bytes < need) return fail(SPM_EINVAL, "spm_contour_invsqrt: scratch too small");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(SPM_EINVAL, "spm_contour_invsqrt: scratch not 256-byte aligned");
     if (overlap(A, out, vb8) || overlap2(A, vb8, scratch, need) || overlap2(out, vb8, scratch, need))
         return fail(SPM_EINVAL, "spm_contour_invsqrt: buffers overlap");
     hipStream_t s = (hipStream_t)stream;
     const int64_t ns = p->n_stored;
-    double *As = static_cast<double *>(scratch), *X = As + ns;
-    char *nsw = reinterpret_cast<char *>(X + ns);
+    double *As = static_cast<double *>(scratch);
+    double *X = reinterpret_cast<double *>(static_cast<char *>(scratch) + vba);
+    char *nsw = static_cast<char *>(scratch) + 2 * vba;
     double *res = reinterpret_cast<double *>(nsw + nsb);
     const bool progress = std::getenv("SPM_PROGRESS") != nullptr;   // one line per node on stderr
     hipLaunchKernelGGL(k_fill, dim3(grid1d(ns, 256)), dim3(256), 0, s, ns, (int)SPM_F64, 0.0, (void *)out);

@@ -723,12 +723,23 @@ void build_groups(spm_pattern_s *p)
             L.count = 0;
             L.smax_r = 0;
             L.smax_c = 0;
+            L.out_tiles = 0;
+            L.exact_macs = 0.0;
+            L.padded_macs = 0.0;
             p->launches.push_back(L);
         }
         auto &B = p->launches.back();
+        const int64_t u = idx[i];
         B.count++;
-        B.smax_r = std::max(B.smax_r, p->grp_s[p->unit_gr[idx[i]]]);
-        B.smax_c = std::max(B.smax_c, p->grp_s[p->unit_gc[idx[i]]]);
+        B.smax_r = std::max(B.smax_r, p->grp_s[p->unit_gr[u]]);
+        B.smax_c = std::max(B.smax_c, p->grp_s[p->unit_gc[u]]);
+        B.padded_macs += cost[u];
+        for (int q = 0; q < 16; ++q) {
+            const int32_t t = p->unit_out[u * 16 + q];
+            if (t < 0) continue;
+            B.out_tiles++;
+            B.exact_macs += p->tile_macs[t];
+        }
     }
 }
 
@@ -796,6 +807,7 @@ void build_layout(spm_pattern_s *p)
     }
     // exact multiply-adds of one product: merge of the two sorted block rows per tile
     std::vector<double> part(16, 0.0);
+    p->tile_macs.assign(nt, 0.0);
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> th;
     for (unsigned w = 0; w < nth; ++w)
@@ -811,7 +823,8 @@ void build_layout(spm_pattern_s *p)
                     else if (*b < *a) ++b;
                     else { k += p->nfun[*a]; ++a; ++b; }
                 }
-                acc += (double)p->nfun[r] * p->nfun[c] * (double)k;
+                p->tile_macs[t] = (double)p->nfun[r] * p->nfun[c] * (double)k;
+                acc += p->tile_macs[t];
             }
             part[w] = acc;
         });
@@ -822,15 +835,16 @@ void build_layout(spm_pattern_s *p)
     p->order.resize(nt);
     for (int64_t t = 0; t < nt; ++t) p->order[t] = (int32_t)t;
     build_groups(p);
+    std::vector<double>().swap(p->tile_macs);   // only the per-class sums are kept
 }
 
 }  // namespace
 
-extern "C" int spm_block_pattern_upload(int64_t n, int32_t nc, const int64_t *cs, const int64_t *brp,
-                                        const int32_t *bcol, void *stream, spm_pattern *out)
+extern "C" int spm_block_pattern_plan(int64_t n, int32_t nc, const int64_t *cs, const int64_t *brp,
+                                      const int32_t *bcol, spm_pattern *out)
 {
-    if (!cs || !brp || !bcol || !out) return fail(SPM_EINVAL, "spm_block_pattern_upload: null pointer");
-    if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_block_pattern_upload: bad n");
+    if (!cs || !brp || !bcol || !out) return fail(SPM_EINVAL, "spm_block_pattern_plan: null pointer");
+    if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_block_pattern_plan: bad n");
     *out = nullptr;
     int st = check_clusters(n, nc, cs);
     if (st) return st;
@@ -860,20 +874,15 @@ extern "C" int spm_block_pattern_upload(int64_t n, int32_t nc, const int64_t *cs
         delete p;
         return fail(SPM_ENOMEM, "host allocation");
     }
-    if ((st = spm::upload_pattern_device(p, (hipStream_t)stream))) {
-        spm::free_pattern_device(p);
-        delete p;
-        return st;
-    }
     *out = p;
     return SPM_OK;
 }
 
-extern "C" int spm_compress_pattern_upload(int64_t n, const int64_t *rp, const int32_t *col, int32_t nc,
-                                           const int64_t *cs, void *stream, spm_pattern *out)
+extern "C" int spm_compress_pattern_plan(int64_t n, const int64_t *rp, const int32_t *col, int32_t nc,
+                                         const int64_t *cs, spm_pattern *out)
 {
-    if (!rp || !col || !cs || !out) return fail(SPM_EINVAL, "spm_compress_pattern_upload: null pointer");
-    if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_compress_pattern_upload: bad n");
+    if (!rp || !col || !cs || !out) return fail(SPM_EINVAL, "spm_compress_pattern_plan: null pointer");
+    if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_compress_pattern_plan: bad n");
     *out = nullptr;
     int st = check_clusters(n, nc, cs);
     if (st) return st;
@@ -927,12 +936,73 @@ extern "C" int spm_compress_pattern_upload(int64_t n, const int64_t *rp, const i
         delete p;
         return fail(SPM_ENOMEM, "host allocation");
     }
-    if ((st = spm::upload_pattern_device(p, (hipStream_t)stream))) {
+    *out = p;
+    return SPM_OK;
+}
+
+// Planned pattern + device tables in a block the library allocates.
+static int upload_owned(spm_pattern p, void *stream, spm_pattern *out)
+{
+    int st;
+    if ((st = spm::upload_pattern_device(p, nullptr, 0, (hipStream_t)stream))) {
         spm::free_pattern_device(p);
         delete p;
+        *out = nullptr;
         return st;
     }
-    *out = p;
+    return SPM_OK;
+}
+
+extern "C" int spm_block_pattern_upload(int64_t n, int32_t nc, const int64_t *cs, const int64_t *brp,
+                                        const int32_t *bcol, void *stream, spm_pattern *out)
+{
+    if (!out) return fail(SPM_EINVAL, "spm_block_pattern_upload: null pointer");
+    const int st = spm_block_pattern_plan(n, nc, cs, brp, bcol, out);
+    return st ? st : upload_owned(*out, stream, out);
+}
+
+extern "C" int spm_compress_pattern_upload(int64_t n, const int64_t *rp, const int32_t *col, int32_t nc,
+                                           const int64_t *cs, void *stream, spm_pattern *out)
+{
+    if (!out) return fail(SPM_EINVAL, "spm_compress_pattern_upload: null pointer");
+    const int st = spm_compress_pattern_plan(n, rp, col, nc, cs, out);
+    return st ? st : upload_owned(*out, stream, out);
+}
+
+extern "C" int spm_pattern_workspace_bytes(spm_pattern p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPM_EINVAL, "spm_pattern_workspace_bytes: null pointer");
+    *bytes = spm::pattern_device_bytes(p);
+    return SPM_OK;
+}
+
+extern "C" int spm_pattern_upload_workspace(spm_pattern p, void *ws, size_t bytes, void *stream)
+{
+    if (!p || !ws) return fail(SPM_EINVAL, "spm_pattern_upload_workspace: null pointer");
+    if (p->uploaded) return fail(SPM_EINVAL, "spm_pattern_upload_workspace: pattern already uploaded");
+    int st = spm::upload_pattern_device(p, ws, bytes, (hipStream_t)stream);
+    if (st) spm::free_pattern_device(p);
+    return st;
+}
+
+extern "C" int spm_pattern_classes(spm_pattern p, int32_t *n_classes, int32_t *row_blocks, int32_t *col_blocks,
+                                   int64_t *units, int64_t *out_tiles, double *exact_macs, double *padded_macs)
+{
+    if (!p || !n_classes) return fail(SPM_EINVAL, "spm_pattern_classes: null pointer");
+    const int32_t nl = (int32_t)p->launches.size();
+    if (row_blocks || col_blocks || units || out_tiles || exact_macs || padded_macs) {
+        if (*n_classes < nl) return fail(SPM_EINVAL, "spm_pattern_classes: arrays too short");
+        for (int32_t i = 0; i < nl; ++i) {
+            const auto &L = p->launches[i];
+            if (row_blocks) row_blocks[i] = L.rb;
+            if (col_blocks) col_blocks[i] = L.cb;
+            if (units) units[i] = L.count;
+            if (out_tiles) out_tiles[i] = L.out_tiles;
+            if (exact_macs) exact_macs[i] = L.exact_macs;
+            if (padded_macs) padded_macs[i] = L.padded_macs;
+        }
+    }
+    *n_classes = nl;
     return SPM_OK;
 }
 

@@ -26,6 +26,13 @@ int fail(int status, const std::string &msg);   // records msg, returns status
             return ::spm::fail(SPM_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Compute calls need the pattern's device tables (a planned pattern has host tables only).
+#define SPM_NEED_DEVICE(p, name)                                                            \
+    do {                                                                                    \
+        if (!(p)->uploaded)                                                                 \
+            return ::spm::fail(SPM_EINVAL, std::string(name) + ": pattern not uploaded");   \
+    } while (0)
+
 // Device copy of a host vector (owned by the pattern / tree handle).
 template <typename T>
 struct DevBuf {
@@ -118,6 +125,9 @@ struct spm_pattern_s {
         int32_t rb, cb, waves;
         int32_t smax_r, smax_c;   // largest slot of the row / column groups of the class
         int64_t first, count;
+        int64_t out_tiles;        // output tiles of the class
+        double exact_macs;        // sum over its output tiles (r, c) of n_r n_c sum_{mu in S_r cap S_c} n_mu
+        double padded_macs;       // multiply-adds the kernels issue for it before block skipping
     };
     std::vector<Launch> launches;
     double padded_macs = 0.0;         // multiply-adds the grouped kernel issues (incl. padding)
@@ -127,7 +137,12 @@ struct spm_pattern_s {
     std::vector<int64_t> csr_rp;      // n + 1
     std::vector<int32_t> csr_col;
     std::vector<int64_t> csr_pos;     // n_stored: CSR position or -1
-    // device copies
+    // device copies: every table is carved from one block of device memory, owned by the
+    // pattern (uploads that allocate) or by the caller (spm_pattern_upload_workspace)
+    bool uploaded = false;
+    void *dev_block = nullptr;
+    bool owns_block = false;
+    std::vector<double> tile_macs;    // n_tiles: exact multiply-adds of each output tile (planning only)
     spm::DevBuf<int64_t> d_cstart, d_blk_rp, d_tile_off, d_colprefix, d_rowbase, d_rowlen, d_csr_pos;
     spm::DevBuf<int64_t> d_pc_rp, d_pc_off, d_pc_g;
     spm::DevBuf<int32_t> d_pc_w;
@@ -141,12 +156,18 @@ struct spm_pattern_s {
 };
 
 namespace spm {
-int upload_pattern_device(spm_pattern_s *p, hipStream_t s);
+size_t pattern_device_bytes(const spm_pattern_s *p);
+// copies the tables into ws (bytes >= pattern_device_bytes), or into a block it
+// allocates when ws is null
+int upload_pattern_device(spm_pattern_s *p, void *ws, size_t bytes, hipStream_t s);
 void free_pattern_device(spm_pattern_s *p);
 }  // namespace spm
 
 namespace spm {
 int launch_gemm(spm_pattern_s *p, int prec, const void *A, int ta, const void *B, int tb, void *C, hipStream_t s);
+size_t gemm_ws_bytes(spm_pattern_s *p, int prec, int ta, int tb);
+int gemm_ws(spm_pattern_s *p, int prec, const void *A, int ta, const void *B, int tb, void *C, void *ws, hipStream_t s);
+size_t ws_align(size_t x);
 int launch_reduce(spm_pattern_s *p, int op, int prec, const void *x, const void *y, const double *vec, double alpha,
                   int post, double scale, double *out, hipStream_t s);
 int launch_axpy(spm_pattern_s *p, int prec, double alpha, const void *X, double beta, void *Y, hipStream_t s);

@@ -408,3 +408,61 @@ def test_fst_vs_oracle(S):
     back = S.fst(t, W, inverse=True).cpu().numpy()
     print(f"fst: relative error vs oracle {err:.3e}, round trip {relerr(back, x):.3e}")
     assert err < TOL64 and relerr(back, x) < TOL64
+
+
+def test_caller_workspace_paths(S, cfg1):
+    """The pattern uploaded into caller memory and the products with a caller workspace
+    give the results of the allocating entry points bit for bit."""
+    print("case: caller-workspace upload and products (cfg1)", flush=True)
+    import ctypes
+    from paper_2211_11681_amd import _lib
+    pat, mask = cfg1["pat"], cfg1["mask"]
+    a = np.where(mask, cfg1["ks"], 0.0)
+    i, j = np.nonzero(mask)
+    b = np.zeros_like(a)
+    b[i, j] = a[i, j] * (1.0 + 0.1 * synth.pair_uniform(206, i, j, 2048))
+    A, B = pat.values_from_csr(to_dev(a[mask])), pat.values_from_csr(to_dev(b[mask]))
+    p2 = S.Pattern.plan_csr(2048, cfg1["rp"], cfg1["col"], cfg1["basis"].cluster_start)
+    assert p2.workspace_bytes() > 0
+    p2.upload_workspace()
+    assert (p2.nnz, p2.n_stored, p2.n_tiles, p2.macs) == (pat.nnz, pat.n_stored, pat.n_tiles, pat.macs)
+    lib = _lib.load()
+    st = lib.spm_pattern_upload_workspace(p2._h, ctypes.c_void_p(p2._ws.data_ptr()), p2._ws.numel() * 8, None)
+    assert st == -1                                     # already uploaded
+    for prec in ("f64", "f32acc", "f32split"):
+        Ap, Bp = (A, B) if prec == "f64" else (S.convert(pat, A, "f64", prec), S.convert(pat, B, "f64", prec))
+        for ta, tb in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+            C1 = pat.empty(prec)
+            S.call("spm_masked_gemm", pat._h, S.prec_code(prec), S._ptr(Ap), ta, S._ptr(Bp), tb, S._ptr(C1),
+                   S._stream())
+            C2 = S.masked_gemm(p2, Ap, Bp, transA=bool(ta), transB=bool(tb), prec=prec)
+            assert torch.equal(C1, C2), (prec, ta, tb)
+        dA1, dB1 = S.masked_gemm_backward(pat, Ap, Bp, Ap, prec=prec)
+        dA2 = pat.empty(prec)
+        dB2 = pat.empty(prec)
+        S.call("spm_masked_gemm_backward", pat._h, S.prec_code(prec), S._ptr(Ap), S._ptr(Bp), S._ptr(Ap),
+               S._ptr(dA2), S._ptr(dB2), S._stream())
+        assert torch.equal(dA1, dA2) and torch.equal(dB1, dB2), prec
+    # a short workspace is refused before any work
+    need = S.gemm_workspace_bytes(pat, "f64", False, False)
+    C = pat.empty("f64")
+    st = lib.spm_masked_gemm_ws(pat._h, 0, ctypes.c_void_p(A.data_ptr()), 0, ctypes.c_void_p(B.data_ptr()), 0,
+                                ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(C.data_ptr()), need - 8, None)
+    assert st == -1 and b"workspace" in lib.spm_last_error()
+
+
+def test_newton_schulz_diverging_reports_enotconv(S, cfg1):
+    """An initial scale far above 2 / lambda_max makes the iteration diverge; three
+    iterations keep every value finite, so the growing residual is what is reported."""
+    print("case: Newton-Schulz diverging from alpha0 = 60 (cfg1)", flush=True)
+    from paper_2211_11681_amd import _lib
+    pat, mask = cfg1["pat"], cfg1["mask"]
+    a = np.where(mask, cfg1["ks"], 0.0)
+    a[np.arange(2048), np.arange(2048)] += 1e-2
+    A = pat.values_from_csr(to_dev(a[mask]))
+    with pytest.raises(_lib.SpmError) as ei:
+        S.newton_schulz(pat, A, 3, 3, "f64", 60.0)
+    assert ei.value.status == -5 and "exceeds the initial residual" in str(ei.value)
+    X, res, _ = S.newton_schulz(pat, A, 3, 3, "f64", 2.0 / 1.02)   # the converging start still passes
+    r = res.cpu().numpy()
+    assert np.all(np.isfinite(r)) and r[-1] < r[0]
