@@ -40,7 +40,7 @@ SIGNATURES = {
     "spm_masked_gemm_ws": [_P, _INT, _P, _INT, _P, _INT, _P, _P, ctypes.c_size_t, _P],
     "spm_masked_gemm_backward": [_P, _INT, _P, _P, _P, _P, _P, _P],
     "spm_masked_gemm_backward_workspace": [_P, _INT, _P],
-    "spm_masked_gemm_backward_ws": [_P, _INT, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
+    "spm_masked_gemm_backward_ws": [_P, _INT, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
     "spm_axpy": [_P, _INT, _D, _P, _D, _P, _P],
     "spm_convert": [_P, _INT, _P, _INT, _P, _P],
     "spm_sqdist": [_P, _INT, _P, _P, _P, _P],

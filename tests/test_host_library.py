@@ -30,6 +30,18 @@ def test_exports_every_declared_symbol(lib):
     assert set(_lib.SIGNATURES) | {"spm_status_string", "spm_last_error"} == names
 
 
+def test_binding_arity_matches_header():
+    """Every ctypes signature has as many arguments as the header's declaration."""
+    hdr = open(os.path.join(ROOT, "include", "spm.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    from paper_2211_11681_amd import _lib
+    for name, args in _lib.SIGNATURES.items():
+        m = re.search(r"\b" + name + r"\s*\(([^)]*)\)\s*;", hdr)
+        assert m, name
+        params = [x for x in m.group(1).split(",") if x.strip() and x.strip() != "void"]
+        assert len(params) == len(args), (name, len(params), len(args))
+
+
 CASES = [("cube2", 2048, 16, 1, 1.6, 1), ("cube3", 4096, 32, 1, 1.0, 2), ("cube2", 4096, 32, 2, 1.6, 3),
          ("sphere", 4096, 32, 1, 1.0, 5), ("cube3", 3000, 32, 1, 1.0, 4), ("cube2", 777, 16, 1, 0.7, 8)]
 
