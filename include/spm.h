@@ -208,6 +208,20 @@ int spm_masked_gemm_workspace(spm_pattern p, int prec, int transA, int transB, s
 int spm_masked_gemm_ws(spm_pattern p, int prec, const void *A, int transA, const void *B, int transB,
                        void *C, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same product with its
+ * workspace in a fixed device array of the library, spm_masked_gemm_noalloc_max_bytes()
+ * bytes (64 MiB) on every device it runs on, held until the process ends.  Nothing
+ * is allocated.  EINVAL when the product needs more workspace than that (the value
+ * arrays of the pattern are then too large: use spm_masked_gemm_ws).  Every call on
+ * one device shares that device's array, so calls that overlap on one GPU (on
+ * different streams, or from several threads) race; calls ordered on one stream are
+ * safe.  The array's contents are left from the last call; each call overwrites the
+ * part it uses before reading it. */
+int spm_masked_gemm_noalloc_max_bytes(size_t *bytes);
+int spm_masked_gemm_noalloc(spm_pattern p, int prec, const void *A, int transA, const void *B, int transB,
+                            void *C, void *stream);
+
 /* Adjoint of C = P_S(A B) (one pattern for all operands):
  * dA = P_S(dC B^T), dB = P_S(A^T dC).  dA or dB may be NULL to skip it.
  * spm_masked_gemm_backward allocates its workspace like spm_masked_gemm;

@@ -38,6 +38,8 @@ SIGNATURES = {
     "spm_masked_gemm": [_P, _INT, _P, _INT, _P, _INT, _P, _P],
     "spm_masked_gemm_workspace": [_P, _INT, _INT, _INT, _P],
     "spm_masked_gemm_ws": [_P, _INT, _P, _INT, _P, _INT, _P, _P, ctypes.c_size_t, _P],
+    "spm_masked_gemm_noalloc_max_bytes": [_P],
+    "spm_masked_gemm_noalloc": [_P, _INT, _P, _INT, _P, _INT, _P, _P],
     "spm_masked_gemm_backward": [_P, _INT, _P, _P, _P, _P, _P, _P],
     "spm_masked_gemm_backward_workspace": [_P, _INT, _P],
     "spm_masked_gemm_backward_ws": [_P, _INT, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],

@@ -2221,6 +2221,60 @@ extern "C" int spm_masked_gemm_ws(spm_pattern p, int prec, const void *A, int ta
     return spm::gemm_ws(p, prec, A, ta, B, tb, C, ws, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------- product without allocation
+// A fixed device array serves as the product's workspace for callers that cannot
+// allocate.  Host code never uses the array's name as an address: its device address
+// is taken once per device with hipGetSymbolAddress and kept in `g_noalloc_ptr`.
+static constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+int noalloc_scratch(void **out)
+{
+    int dev = 0;
+    SPM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPM_EUNSUPPORTED, "spm_masked_gemm_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SPM_EHIP, std::string("spm_masked_gemm_noalloc: hipGetSymbolAddress failed: ") +
+                                      hipGetErrorString(e));
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return SPM_OK;
+}
+}  // namespace
+
+extern "C" int spm_masked_gemm_noalloc_max_bytes(size_t *bytes)
+{
+    if (!bytes) return fail(SPM_EINVAL, "spm_masked_gemm_noalloc_max_bytes: null pointer");
+    *bytes = kNoAllocScratchBytes;
+    return SPM_OK;
+}
+
+extern "C" int spm_masked_gemm_noalloc(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C,
+                                       void *stream)
+{
+    int st = check_gemm_args(p, prec, A, ta, B, tb, C, "spm_masked_gemm_noalloc");
+    if (st) return st;
+    const size_t need = spm::gemm_ws_bytes(p, prec, ta, tb);
+    if (need > kNoAllocScratchBytes)
+        return fail(SPM_EINVAL, "spm_masked_gemm_noalloc: the product needs " + std::to_string(need) +
+                                    " bytes of workspace, above the fixed " + std::to_string(kNoAllocScratchBytes) +
+                                    " (use spm_masked_gemm_ws with a caller workspace)");
+    void *ws = nullptr;
+    if (need && (st = noalloc_scratch(&ws))) return st;
+    return spm::gemm_ws(p, prec, A, ta, B, tb, C, ws, (hipStream_t)stream);
+}
+
 static size_t backward_ws_bytes(spm_pattern p, int prec)
 {
     return std::max(spm::gemm_ws_bytes(p, prec, 0, 1), spm::gemm_ws_bytes(p, prec, 1, 0));
