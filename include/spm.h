@@ -122,10 +122,16 @@ int spm_block_pattern_upload(int64_t n, int32_t n_clusters, const int64_t *clust
  * above is plan + spm_pattern_upload_workspace into a block the library allocates).
  * spm_block_pattern_plan / spm_compress_pattern_plan: the same validation, tile
  * layout, transpose map and schedule as the uploads, on the host only (EPATTERN,
- * EINVAL, EUNSUPPORTED as above).  The handle answers spm_pattern_info,
- * spm_pattern_tiles, spm_pattern_download_csr, spm_pattern_classes and
- * spm_pattern_workspace_bytes; every compute call on it returns EINVAL until it is
- * uploaded.
+ * EINVAL, EUNSUPPORTED as above).  cluster_level (host, n_clusters values in
+ * [0, 64), or NULL): the tree level of every cluster.  With levels the middle
+ * clusters of the product are ordered level by level and no stage of the schedule
+ * mixes two levels, which the split-precision product (SPM_F32SPLIT) needs to scale
+ * its operands per row and level; without them SPM_F32SPLIT runs on the per-tile
+ * compensated kernel.  The handle answers spm_pattern_info, spm_pattern_tiles,
+ * spm_pattern_download_csr, spm_pattern_classes and spm_pattern_workspace_bytes;
+ * every compute call on it returns EINVAL until it is uploaded.
+ * spm_pattern_upload: device tables in a block the library allocates (freed by
+ * spm_pattern_destroy).
  * spm_pattern_workspace_bytes: device bytes of the pattern's tables.
  * spm_pattern_upload_workspace: copies the tables into the caller's device memory ws
  * (at least that many bytes, 256-byte aligned); the pattern keeps pointers into ws,
@@ -133,9 +139,11 @@ int spm_block_pattern_upload(int64_t n, int32_t n_clusters, const int64_t *clust
  * not free it).  Synchronous (blocking copies).  EINVAL on a short or misaligned
  * workspace or a pattern already uploaded. */
 int spm_block_pattern_plan(int64_t n, int32_t n_clusters, const int64_t *cluster_start,
-                           const int64_t *blk_row_ptr, const int32_t *blk_col, spm_pattern *out);
+                           const int64_t *blk_row_ptr, const int32_t *blk_col, const int32_t *cluster_level,
+                           spm_pattern *out);
 int spm_compress_pattern_plan(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int32_t n_clusters,
-                              const int64_t *cluster_start, spm_pattern *out);
+                              const int64_t *cluster_start, const int32_t *cluster_level, spm_pattern *out);
+int spm_pattern_upload(spm_pattern p, void *stream);
 int spm_pattern_workspace_bytes(spm_pattern p, size_t *bytes);
 int spm_pattern_upload_workspace(spm_pattern p, void *ws, size_t bytes, void *stream);
 

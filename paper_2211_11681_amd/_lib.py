@@ -23,8 +23,9 @@ SIGNATURES = {
     "spm_tree_block_pattern": [_P, _D, _P, _P, _P],
     "spm_compress_pattern_upload": [_I64, _P, _P, _I32, _P, _P, _P],
     "spm_block_pattern_upload": [_I64, _I32, _P, _P, _P, _P, _P],
-    "spm_block_pattern_plan": [_I64, _I32, _P, _P, _P, _P],
-    "spm_compress_pattern_plan": [_I64, _P, _P, _I32, _P, _P],
+    "spm_block_pattern_plan": [_I64, _I32, _P, _P, _P, _P, _P],
+    "spm_compress_pattern_plan": [_I64, _P, _P, _I32, _P, _P, _P],
+    "spm_pattern_upload": [_P, _P],
     "spm_pattern_workspace_bytes": [_P, _P],
     "spm_pattern_upload_workspace": [_P, _P, ctypes.c_size_t, _P],
     "spm_pattern_classes": [_P, _P, _P, _P, _P, _P, _P, _P],

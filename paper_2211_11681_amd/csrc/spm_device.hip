@@ -42,6 +42,9 @@ void for_each_table(spm_pattern_s *p, F &&f)
     f(p->d_unit_order, p->unit_order); f(p->d_pair_off, p->pair_off); f(p->d_pair_a, p->pair_a);
     f(p->d_pair_b, p->pair_b); f(p->d_gl_nm, p->gl_nm); f(p->d_gl_offd, p->gl_offd);
     f(p->d_stage_off, p->stage_off); f(p->d_stage_first, p->stage_first); f(p->d_csr_pos, p->csr_pos);
+    f(p->d_clevel, p->clevel); f(p->d_gl_nml, p->gl_nml); f(p->d_gl_offT, p->gl_offT);
+    f(p->d_stage_off_lv, p->stage_off_lv); f(p->d_stage_first_lv, p->stage_first_lv);
+    f(p->d_pair_a_lv, p->pair_a_lv); f(p->d_pair_b_lv, p->pair_b_lv);
 }
 
 int64_t partial_count(const spm_pattern_s *p) { return (p->n_tiles + kRedTiles - 1) / kRedTiles + 1; }
@@ -932,10 +935,23 @@ struct UnitInfo {
     int nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3;
 };
 
-template <int LEAD>
+// Stage record of the split-precision product (its operands are stored k-contiguous,
+// in the layout of the transposed tiles): per k pair p (k rows 2p, 2p + 1, always in one
+// cluster since every cluster size is even) and member slot, the element offset of
+// (member row 0, k row 2p) in the tile (mu, member), -1 where the tile is absent or the
+// rows are padding; the lane adds (its member row) x nmu[p].
+struct OzTab {
+    int64_t kofs[16][8];
+    int32_t nmu[16];      // functions of the k pair's cluster (row stride of its tiles)
+    int32_t ks;           // k rows of the stage
+    int32_t level;        // tree level of the stage's clusters, -1 for an empty stage
+    int32_t pad[2];
+};
+
+template <int LEAD, typename Rec = KTab>
 constexpr size_t ring_bytes()
 {
-    return (((LEAD + 1) * sizeof(KTab) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
+    return (((LEAD + 1) * sizeof(Rec) + 15) & ~(size_t)15) + 4 * (128 * 8 + 3 * 64 * 4);
 }
 
 // The fragment that every consumer wave of a unit needs (the unit's single 16-row side),
@@ -947,15 +963,19 @@ struct SharedSide {
     const double *X;     // operand of the shared side
     double *dst;         // LDS ring, 512 doubles per slot
     int slot;            // record column of the lane's member
-    int ipair;           // offset of the lane's row pair inside a tile column
+    int ipair;           // offset of the lane's row pair inside a tile column (split-precision
+                         // records: the lane's row inside its member)
     int kodd;            // 1 on odd lanes
     bool ok;             // the lane's row exists
 };
 
-template <int LEAD, bool SHARE>
-__device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *lds, KTab *ring, int lane,
+template <int LEAD, bool SHARE, typename Rec = KTab>
+__device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *lds, Rec *ring, int lane,
                                 const SharedSide &sh)
 {
+    // OzTab records: g.gl_offd holds the offsets of the transposed tiles (mu, member) and
+    // g.gl_nm the cluster size | level << 8 (the caller passes those tables)
+    constexpr bool OZ = std::is_same<Rec, OzTab>::value;
     const int64_t s0 = ui.s0, p0 = ui.p0;
     const int nst = ui.nst, npairs = ui.npairs, ngr = ui.ngr, ngc = ui.ngc;
     const int nr0 = ui.nr0, nr1 = ui.nr1, nr2 = ui.nr2, nr3 = ui.nr3;
@@ -987,7 +1007,7 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         int32_t nm[64], ent[64], bnd[64];
     };
     constexpr int kSlots = LEAD + 1;
-    Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((kSlots * sizeof(KTab) + 15) & ~(size_t)15));
+    Staging *stg = reinterpret_cast<Staging *>(reinterpret_cast<char *>(lds) + ((kSlots * sizeof(Rec) + 15) & ~(size_t)15));
     auto dma4 = [&](const void *src, void *dst) {
         __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
     };
@@ -1007,7 +1027,49 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
         dma16(g.gl_offd + (int64_t)ec * 4 + tk, P->off);
         dma4(g.gl_nm + ec, P->nm);
     };
-    auto write_tab = [&](KTab *T, int64_t o_raw, int32_t m_raw, bool ok, int t_np) {
+    // OzTab writer shared by both paths: the stage's cluster sizes nmv (uniform), the
+    // lane's k pair kp = lane % 16 and slot group sg = lane / 16 (slots sg and sg + 4);
+    // off_of(m, sl) is the tile offset of pair m's cluster for slot sl
+    auto write_oz = [&](OzTab *T, uint32_t Bw, uint32_t Lw, int kb, int lev0, auto &&off_of, auto &&nm_of) {
+        const int kp = lane & 15, sg = lane >> 4, k = 2 * kp;
+        const bool live = ((Lw >> k) & 1u) != 0;
+        const uint32_t prefix = Bw & ((2u << k) - 1u);
+        const int m = __builtin_popcount(prefix) - 1;
+        const int kkm = k - (prefix ? 31 - __builtin_clz(prefix) : 0);
+        const int mm = m < 0 ? 0 : m;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int sl = sg + 4 * h;
+            const int64_t o = off_of(mm, sl);
+            T->kofs[kp][sl] = (live && o >= 0) ? o + kkm : -1;
+        }
+        const int nmm = nm_of(mm);
+        if (sg == 0) T->nmu[kp] = live ? nmm : 0;
+        if (lane == 0) {
+            T->ks = kb;
+            T->level = kb > 0 ? lev0 : -1;
+        }
+    };
+    auto write_tab = [&](Rec *T, int64_t o_raw, int32_t m_raw, bool ok, int t_np) {
+        if constexpr (OZ) {
+            const int64_t t_off = (ok && tvalid) ? o_raw : -1;
+            const int t_nml = (ok && tslot == 0) ? m_raw : 0;
+            uint32_t Bm = 0, Lm = 0;
+            int kb = 0;
+            const int lev0 = __builtin_amdgcn_readlane(t_nml, 0) >> 8;
+#pragma unroll
+            for (int q = 0; q < kSP; ++q) {
+                const int nmq = __builtin_amdgcn_readlane(t_nml, q * 8) & 0xFF;
+                if (q < t_np) {
+                    Bm |= 1u << kb;
+                    Lm |= (nmq >= 32 ? 0xFFFFFFFFu : ((1u << nmq) - 1u)) << kb;
+                    kb += nmq;
+                }
+            }
+            write_oz(T, Bm, Lm, kb, lev0, [&](int m, int sl) { return __shfl(t_off, m * 8 + sl); },
+                     [&](int m) { return __shfl(t_nml, m * 8) & 0xFF; });
+            return;
+        } else {
         const int64_t t_off = (ok && tvalid) ? o_raw : -1;
         const int t_nm = (ok && tslot == 0) ? m_raw : 0;
         int nmv[kSP], kbv[kSP];
@@ -1037,24 +1099,31 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
             T->kofs[kk][(rows ? 0 : 4) + q] = (live && o >= 0) ? o + (int64_t)kkm * nslot[q] : -1;
         }
         if (lane == 0) T->ks = kacc;
+        }
     };
     // The same record built from the staging set of the loop: the stage's cluster sizes go
     // to scalar registers, whose bit masks of cluster starts (B) and of live rows (L) give
     // each lane kk its cluster (the set bits of B up to kk) and whether row kk exists; the
     // tile offsets are read from the staged copy of the union entries.
-    auto write_tab_stg = [&](KTab *T, const Staging *P, int32_t m_raw, bool ok, int t_np) {
+    auto write_tab_stg = [&](Rec *T, const Staging *P, int32_t m_raw, bool ok, int t_np) {
         const int t_nm = (ok && tslot == 0) ? m_raw : 0;
         uint64_t Bm = 0, Lm = 0;
         int kb = 0;
 #pragma unroll
         for (int q = 0; q < kSP; ++q) {
-            const int nmq = __builtin_amdgcn_readlane(t_nm, q * 8);
+            const int nmq = __builtin_amdgcn_readlane(t_nm, q * 8) & (OZ ? 0xFF : ~0);
             if (q < t_np) {
                 Bm |= 1ull << kb;
                 Lm |= ((1ull << nmq) - 1) << kb;
                 kb += nmq;
             }
         }
+        if constexpr (OZ) {
+            const int lev0 = __builtin_amdgcn_readlane(t_nm, 0) >> 8;
+            write_oz(T, (uint32_t)Bm, (uint32_t)Lm, kb, lev0, [&](int m, int sl) { return P->off[2 * (m * 8 + sl)]; },
+                     [&](int m) { return __shfl(t_nm, m * 8) & 0xFF; });
+            return;
+        } else {
         const int kk = lane & 31;
         const bool rows = lane < 32;
         const uint32_t Bw = (uint32_t)Bm, Lw = (uint32_t)Lm;
@@ -1070,17 +1139,33 @@ __device__ void record_producer(const GroupArgs &g, const UnitInfo &ui, double *
             T->kofs[kk][sl] = (live && o >= 0) ? o + (int64_t)kkm * nslot[q] : -1;
         }
         if (lane == 0) T->ks = kb;
+        }
     };
     // copy of the shared fragment of the record just written to ring slot t_slot (the
     // record is re-read from LDS: this wave wrote it, and LDS accesses of a wave are ordered)
-    auto share = [&](const KTab *T, int t_slot) {
-        if constexpr (SHARE) {
+    auto share = [&](const Rec *T, int t_slot) {
+        if constexpr (SHARE && !OZ) {
             double *d = sh.dst + t_slot * 512;
             const int lk = lane >> 4;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t o = T->kofs[4 * (2 * q + sh.kodd) + lk][sh.slot];
                 dma16((sh.ok && o >= 0) ? sh.X + o + sh.ipair : g_zero_word, d + q * 128);
+            }
+        } else if constexpr (SHARE && OZ) {
+            // the split-precision slices: lane L copies what consumer lane L loads, the k pair
+            // 4 (L / 16) + q of its row (sh.ipair = the row inside the member), 16 bytes
+            double *d = sh.dst + t_slot * 512;
+            const int lk = lane >> 4;
+            const uint4 *const X4 = reinterpret_cast<const uint4 *>(sh.X);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pp = 4 * lk + q;
+                const int64_t o = T->kofs[pp][sh.slot];
+                const int nmu = T->nmu[pp];
+                const void *src = (sh.ok && o >= 0) ? (const void *)(X4 + ((o + (int64_t)sh.ipair * nmu) >> 1))
+                                                    : (const void *)g_zero_word;
+                dma16(src, d + q * 128);
             }
         }
     };
@@ -1599,6 +1684,381 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_f32acc(GroupArgs g, const 
     }
 }
 
+// ---------------------------------------------------------------- split-precision product on matrix cores
+// F32SPLIT: operands hi + lo (FP32 pairs, exact in FP64).  Every value x of row i of an
+// operand whose column cluster lies on tree level L is scaled by 2^-e, e = e(i, L) the
+// exponent of the largest |x| over that row and level (so |x 2^-e| < 1), and cut into
+// four 8-bit slices, x 2^-e = sum_s sigma_s 2^-8s up to 2^-33 (round to nearest at each
+// step: |sigma_1| <= 256, |sigma_s| <= 128 after; integers of at most 8 significant bits,
+// exact in bf16).  That is the error-free splitting of Ozaki, Ogita, Oishi and Rump
+// (2012) with one exponent per row and level.  Products of slices are exact in FP32 (at
+// most 16 bits), and a stage's sums over its 32 k rows (one level) stay below 2^24, so the
+// matrix core's FP32 accumulation is exact; the slice pairs (s, t) with s + t <= 5 of one
+// weight 2^-8(s+t) share an accumulator.  The stage sums are combined in FP64 with the
+// row and column exponents of their level, which keeps the error near 2^-32 of each
+// row-and-level maximum.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kOzSlices = 4;
+constexpr int kOzNoExp = -100000;      // a row and level without a nonzero value
+
+// One workgroup per block row r of the operand view V (rows of op(A), or columns of op(B)
+// as rows of op(B)^T); its waves take the row's tiles in turn, the lanes of a wave the
+// elements of a tile.  Element (i, k) of view tile t = (r, mu) is read from the source
+// tile t, column-major (i, k) at k n_r + i (rowsrc = 0), or from the source tile trans[t]
+// = (mu, r), column-major (k, i) at i n_mu + k (rowsrc = 1).  Pass 1 forms e(i, L) in LDS
+// (integer maxima: the result does not depend on the order); pass 2 writes the slices of
+// element (i, k) at position d = tile_off[trans t] + i n_mu + k (the transposed tile, rows
+// k-contiguous): the k pair (d, d + 1), d even, is 16 bytes holding (sigma_s(d),
+// sigma_s(d + 1)) for s = 1..4.  Every cluster size is even.
+constexpr int kSliceWaves = 8;
+
+__global__ __launch_bounds__(64 * kSliceWaves) void k_oz_slice(int32_t nc, int32_t nlev, int rowsrc, int64_t ns,
+                                                  const int64_t *__restrict__ blk_rp, const int32_t *__restrict__ tile_col,
+                                                  const int64_t *__restrict__ tile_off, const int32_t *__restrict__ trans,
+                                                  const int32_t *__restrict__ nfun, const int64_t *__restrict__ cstart,
+                                                  const int32_t *__restrict__ clevel, const float *__restrict__ X,
+                                                  uint4 *__restrict__ S, int32_t *__restrict__ expo)
+{
+    extern __shared__ int emax[];            // kMax x nlev
+    const int r = blockIdx.x;
+    if (r >= nc) return;
+    const int nr = nfun[r];
+    if (nr == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int x = threadIdx.x; x < nr * nlev; x += blockDim.x) emax[x] = kOzNoExp;
+    __syncthreads();
+    const int64_t t0 = blk_rp[r], t1 = blk_rp[r + 1];
+    for (int64_t t = t0 + wave; t < t1; t += kSliceWaves) {
+        const int mu = tile_col[t], nm = nfun[mu], L = clevel[mu];
+        const int64_t base = rowsrc ? tile_off[trans[t]] : tile_off[t];
+        for (int e = lane; e < nr * nm; e += 64) {
+            const int i = e / nm, k = e - i * nm;
+            const int64_t q = base + (rowsrc ? (int64_t)i * nm + k : (int64_t)k * nr + i);
+            const double x = (double)X[q] + (double)X[ns + q];
+            if (x != 0.0) atomicMax(&emax[i * nlev + L], ilogb(fabs(x)) + 1);
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < nr * nlev; x += blockDim.x) expo[(cstart[r] + x / nlev) * nlev + x % nlev] = emax[x];
+    for (int64_t t = t0 + wave; t < t1; t += kSliceWaves) {
+        const int mu = tile_col[t], nm = nfun[mu], L = clevel[mu];
+        const int np = nm >> 1;
+        const int64_t d0 = tile_off[trans[t]];
+        const int64_t base = rowsrc ? d0 : tile_off[t];
+        for (int e = lane; e < nr * np; e += 64) {
+            const int i = e / np, k = 2 * (e - i * np);
+            const int ex = emax[i * nlev + L];
+            const int sh = ex == kOzNoExp ? 0 : -ex;
+            uint32_t w[kOzSlices];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t q = base + (rowsrc ? (int64_t)i * nm + k + h : (int64_t)(k + h) * nr + i);
+                double y = ldexp((double)X[q] + (double)X[ns + q], sh);
+#pragma unroll
+                for (int sl = 0; sl < kOzSlices; ++sl) {
+                    y = y * 256.0;
+                    const double sg = rint(y);
+                    y = y - sg;
+                    const uint32_t bits = __float_as_uint((float)sg) >> 16;     // exact in bf16
+                    w[sl] = h == 0 ? bits : (w[sl] | bits << 16);
+                }
+            }
+            S[(d0 + (int64_t)i * nm + k) >> 1] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+struct OzArgs {
+    const int32_t *exp_a, *exp_b;     // e(i, L) of the two views, n x nlev
+    const int64_t *cstart;
+    int32_t nlev;
+};
+
+// Register-direct split-precision product on the unit schedule.  Workgroup = one unit, or
+// one block row of a unit with several block rows and columns; every consumer wave owns
+// one 16 x 16 output block (a block row of a unit with one column block, else a column
+// block), and the last wave keeps the stage records.  Per stage a lane needs, for its row
+// and its 8 k rows (4 k pairs), the four slices of both operands (16 bytes per k pair and
+// operand).  SHARE (several consumers): the side all consumers share (the unit's single
+// 16-row block row, else its single column block) is copied to LDS by the record wave
+// LEAD = 5 stages ahead, and each consumer loads only its own side; otherwise both sides
+// are loaded.  The loads of a consumer run two stages ahead in a ring of three register
+// sets (the level-homogeneous stage lists have a multiple of three stages per unit).  The
+// slice pairs go to v_mfma_f32_16x16x32_bf16; accumulators of one weight hold exact
+// integer sums for at most four stages of one level, then are added in FP64 scaled by
+// 2^(e_row + e_col - 8 (s + t)).
+// register sets of the consumer ring: three without SHARE (both sides loaded), two with it
+// (fewer registers, so that two 8-wave workgroups fit a CU); the level-homogeneous stage
+// lists have a multiple of six stages per unit
+
+template <int WAVES, bool SHARE>
+__global__ __launch_bounds__(WAVES * 64, SHARE ? 4 : 1) void k_mgemm_oz(GroupArgs g, OzArgs z, int rows_split, int sub_rows,
+                                                        const uint4 *__restrict__ SA, const uint4 *__restrict__ SB,
+                                                        float *__restrict__ C, int64_t ns)
+{
+    constexpr int LEAD = SHARE ? 5 : 3;
+    constexpr int kSlots = LEAD + 1;
+    extern __shared__ double lds[];
+    OzTab *ring = reinterpret_cast<OzTab *>(lds);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // workgroup -> (unit, fixed block row): the sub_rows block rows of one unit go to
+    // workgroups 8 apart, which the round-robin dispatch puts on one XCD (one L2)
+    int64_t uidx = blockIdx.x;
+    int rbf = 0;
+    if (sub_rows > 1) {
+        const int64_t grp = uidx / (8 * sub_rows), within = uidx % (8 * sub_rows);
+        rbf = (int)(within / 8);
+        uidx = grp * 8 + within % 8;
+    }
+    if (uidx >= g.count) return;
+    const int u = g.unit_order[g.first + uidx];
+    const int gr = g.unit_gr[u], gc = g.unit_gc[u];
+    const int sr = g.grp_s[gr], sc = g.grp_s[gc];
+    const int ngr = g.grp_g[gr], ngc = g.grp_g[gc];
+    const int nr0 = g.nfun[g.grp_mem[gr * 4]];
+    const int nr1 = ngr > 1 ? g.nfun[g.grp_mem[gr * 4 + 1]] : 0;
+    const int nr2 = ngr > 2 ? g.nfun[g.grp_mem[gr * 4 + 2]] : 0;
+    const int nr3 = ngr > 3 ? g.nfun[g.grp_mem[gr * 4 + 3]] : 0;
+    const int nc0 = g.nfun[g.grp_mem[gc * 4]];
+    const int nc1 = ngc > 1 ? g.nfun[g.grp_mem[gc * 4 + 1]] : 0;
+    const int nc2 = ngc > 2 ? g.nfun[g.grp_mem[gc * 4 + 2]] : 0;
+    const int nc3 = ngc > 3 ? g.nfun[g.grp_mem[gc * 4 + 3]] : 0;
+    const int nconsumer = rows_split ? g.RB : g.CB;
+    const int producer = WAVES - 1;
+    const int64_t s0 = g.stage_off[u], p0 = g.pair_off[u];
+    const int nst = (int)(g.stage_off[u + 1] - s0), npairs = (int)(g.pair_off[u + 1] - p0);
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nlev = z.nlev;
+    // LDS after the record ring and staging: the shared-side slots (SHARE), then the
+    // exponent tables of the workgroup's rows and columns
+    double *const shr = lds + ring_bytes<LEAD, OzTab>() / sizeof(double);
+    const int erows = rows_split ? 16 * g.RB : 16, ecols = rows_split ? 16 : 16 * g.CB;
+    const int erow0 = rows_split ? 0 : 16 * rbf;
+    int *const ea = reinterpret_cast<int *>(reinterpret_cast<char *>(shr) + (SHARE ? kSlots * 4096 : 0));
+    int *const eb = ea + erows * nlev;
+    // the shared side: the rows (block row rb, all consumers own column blocks) unless the
+    // consumers own block rows
+    const bool shA = !rows_split;
+    const int rb_sh = rbf;                            // block row of the shared rows
+
+    if (wave == producer) {
+        const UnitInfo ui{s0, p0, nst, npairs, ngr, ngc, nr0, nr1, nr2, nr3, nc0, nc1, nc2, nc3};
+        SharedSide sh{};
+        if constexpr (SHARE) {
+            const int ssz = shA ? sr : sc, sng = shA ? ngr : ngc;
+            const int x = shA ? 16 * rb_sh + lr : lr;        // rows of block rb_sh, or of column block 0
+            const int kx = x / ssz, ix = x - kx * ssz;
+            sh.X = reinterpret_cast<const double *>(shA ? SA : SB);
+            sh.dst = shr;
+            sh.slot = (shA ? 0 : 4) + (kx & 3);
+            sh.ipair = ix;
+            sh.ok = kx < sng && ix < (shA ? sel4(kx & 3, nr0, nr1, nr2, nr3) : sel4(kx & 3, nc0, nc1, nc2, nc3));
+        }
+        record_producer<LEAD, SHARE, OzTab>(g, ui, lds, ring, lane, sh);
+        return;
+    }
+    // consumers fill the exponent tables (visible after the first barrier)
+    for (int x = tid; wave < nconsumer && x < (erows + ecols) * nlev; x += 64 * nconsumer) {
+        const bool isr = x < erows * nlev;
+        const int y = isr ? x : x - erows * nlev;
+        const int rc = y / nlev, L = y - rc * nlev;
+        const int pos = isr ? erow0 + rc : rc;
+        const int ss = isr ? sr : sc, ngg = isr ? ngr : ngc;
+        const int km = pos / ss, ii = pos - km * ss;
+        int v = kOzNoExp;
+        if (km < ngg) {
+            const int cl = g.grp_mem[(isr ? gr : gc) * 4 + km];
+            if (ii < g.nfun[cl]) v = (isr ? z.exp_a : z.exp_b)[(z.cstart[cl] + ii) * nlev + L];
+        }
+        (isr ? ea : eb)[y] = v;
+    }
+    if (wave >= nconsumer) {
+        lds_barrier();
+        for (int s = 0; s < nst; ++s) lds_barrier();
+        return;
+    }
+    const int rb = rows_split ? wave : rbf, cb = rows_split ? 0 : wave;
+    const int ra = 16 * rb + lr, kra = ra / sr, ia = ra - kra * sr;
+    const bool oka = kra < ngr && ia < sel4(kra & 3, nr0, nr1, nr2, nr3);
+    const int slota = kra & 3;
+    const int cbb = 16 * cb + lr, kcb = cbb / sc, jb = cbb - kcb * sc;
+    const bool okb = kcb < ngc && jb < sel4(kcb & 3, nc0, nc1, nc2, nc3);
+    const int slotb = 4 + (kcb & 3);
+    // absent k pairs load 16 zero bytes from a global word (a pointer select, so that every
+    // load is a global load issued unconditionally)
+    const u32x4 *const zero4 = reinterpret_cast<const u32x4 *>(g_zero_word);
+    const u32x4 *const A4 = reinterpret_cast<const u32x4 *>(SA), *const B4 = reinterpret_cast<const u32x4 *>(SB);
+    // a lane's four k pairs of one operand: member q holds the k pair 4 lk + q, word s of
+    // it the two bf16 values of slice s
+    struct Frag {
+        u32x4 q0, q1, q2, q3;
+    };
+    auto load_side = [&](const OzTab *T, int slot, bool ok, int row, const u32x4 *base, Frag &f) {
+        auto one = [&](int pp) {
+            const int64_t o = T->kofs[pp][slot];
+            const int nmu = T->nmu[pp];
+            return *((ok && o >= 0) ? base + ((o + (int64_t)row * nmu) >> 1) : zero4);
+        };
+        const int p0 = 4 * lk;
+        f.q0 = one(p0);
+        f.q1 = one(p0 + 1);
+        f.q2 = one(p0 + 2);
+        f.q3 = one(p0 + 3);
+    };
+    // own side (the block the wave owns) and, without SHARE, the other side too
+    auto load_stage = [&](const OzTab *T, Frag &fo, Frag &fx) {
+        if (SHARE) {
+            if (shA) load_side(T, slotb, okb, jb, B4, fo);
+            else load_side(T, slota, oka, ia, A4, fo);
+        } else {
+            load_side(T, slota, oka, ia, A4, fx);
+            load_side(T, slotb, okb, jb, B4, fo);
+        }
+    };
+    flt4 P0 = flt4{0.f, 0.f, 0.f, 0.f}, P1 = P0, P2 = P0, P3 = P0;
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    // this lane's output rows (16 rb + 4 lk + r) and column in the exponent tables
+    const int erl = 16 * rb - erow0 + 4 * lk, ecl = 16 * cb + lr;
+    auto flush = [&](int L) {
+        const int ecv = eb[ecl * nlev + L];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int erv = ea[(erl + r) * nlev + L];
+            // exact: four integers below 2^24 at weights 2^-16 .. 2^-40 span 48 bits
+            double t = (double)P0[r] * 0x1p-16;
+            t += (double)P1[r] * 0x1p-24;
+            t += (double)P2[r] * 0x1p-32;
+            t += (double)P3[r] * 0x1p-40;
+            if (erv != kOzNoExp && ecv != kOzNoExp) acc[r] += ldexp(t, erv + ecv);
+        }
+        P0 = flt4{0.f, 0.f, 0.f, 0.f};
+        P1 = P0;
+        P2 = P0;
+        P3 = P0;
+    };
+    auto mfmas = [&](const Frag &fa, const Frag &fb) {
+        const bf16x8 a0 = (bf16x8)(u32x4){fa.q0.x, fa.q1.x, fa.q2.x, fa.q3.x};
+        const bf16x8 a1 = (bf16x8)(u32x4){fa.q0.y, fa.q1.y, fa.q2.y, fa.q3.y};
+        const bf16x8 a2 = (bf16x8)(u32x4){fa.q0.z, fa.q1.z, fa.q2.z, fa.q3.z};
+        const bf16x8 a3 = (bf16x8)(u32x4){fa.q0.w, fa.q1.w, fa.q2.w, fa.q3.w};
+        const bf16x8 b0 = (bf16x8)(u32x4){fb.q0.x, fb.q1.x, fb.q2.x, fb.q3.x};
+        const bf16x8 b1 = (bf16x8)(u32x4){fb.q0.y, fb.q1.y, fb.q2.y, fb.q3.y};
+        const bf16x8 b2 = (bf16x8)(u32x4){fb.q0.z, fb.q1.z, fb.q2.z, fb.q3.z};
+        const bf16x8 b3 = (bf16x8)(u32x4){fb.q0.w, fb.q1.w, fb.q2.w, fb.q3.w};
+        // weight classes w = s + t (0-based slice indices)
+        P0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, P0, 0, 0, 0);
+        P1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, P1, 0, 0, 0);
+        P2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, P2, 0, 0, 0);
+        P3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b3, P3, 0, 0, 0);
+        P1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, P1, 0, 0, 0);
+        P2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, P2, 0, 0, 0);
+        P3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, P3, 0, 0, 0);
+        P2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, P2, 0, 0, 0);
+        P3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, P3, 0, 0, 0);
+        P3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b0, P3, 0, 0, 0);
+    };
+    int cur = -1, cnt = 0;
+    // stage in ring slot `slot`: the own side in fo (and fx without SHARE), the shared side
+    // from its LDS slot (the same index: both rings have kSlots slots)
+    auto stage = [&](int slot, const Frag &fo, const Frag &fx) {
+        const OzTab *T = &ring[slot];
+        const int lv = T->level;                                 // wave-uniform
+        if (lv < 0) return;                                      // empty stage
+        if (cur >= 0 && (lv != cur || cnt == 4)) {
+            flush(cur);
+            cnt = 0;
+        }
+        cur = lv;
+        if (SHARE) {
+            // the shared side straight from LDS into operand order: word s of k pair q of this
+            // lane sits at ((q * 64 + lane) * 4 + s) words
+            const uint32_t *sp = reinterpret_cast<const uint32_t *>(shr + slot * 512) + 4 * lane;
+            Frag fs;
+            fs.q0 = (u32x4){sp[0], sp[1], sp[2], sp[3]};
+            fs.q1 = (u32x4){sp[256], sp[257], sp[258], sp[259]};
+            fs.q2 = (u32x4){sp[512], sp[513], sp[514], sp[515]};
+            fs.q3 = (u32x4){sp[768], sp[769], sp[770], sp[771]};
+            if (shA) mfmas(fs, fo);
+            else mfmas(fo, fs);
+        } else {
+            mfmas(fx, fo);
+        }
+        ++cnt;
+    };
+    auto nxt = [&](int x) { return x == kSlots - 1 ? 0 : x + 1; };
+    lds_barrier();
+    // records 0 .. LEAD - 1 are in the ring when the loop starts; past the last stage the
+    // records have no rows and the loads read zeros
+    int sl0 = 0;                                                 // ring slot of stage s
+    if constexpr (SHARE) {
+        // two sets: stage s + 1 is loaded while stage s runs
+        Frag o0, o1, x0;
+        load_stage(&ring[0], o0, x0);
+        for (int s = 0; s < nst; s += 2) {
+            const int sl1 = nxt(sl0);
+            load_stage(&ring[sl1], o1, x0);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(sl0, o0, x0);
+            lds_barrier();
+            const int sl2 = nxt(sl1);
+            load_stage(&ring[sl2], o0, x0);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(sl1, o1, x0);
+            lds_barrier();
+            sl0 = sl2;
+        }
+    } else {
+        // three sets: stage s + 2 is loaded while stage s runs
+        Frag o0, o1, o2, x0, x1, x2;
+        load_stage(&ring[0], o0, x0);
+        load_stage(&ring[1], o1, x1);
+        for (int s = 0; s < nst; s += 3) {
+            const int sl1 = nxt(sl0), sl2 = nxt(sl1);
+            load_stage(&ring[sl2], o2, x2);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(sl0, o0, x0);
+            lds_barrier();
+            const int sl3 = nxt(sl2);
+            load_stage(&ring[sl3], o0, x0);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(sl1, o1, x1);
+            lds_barrier();
+            const int sl4 = nxt(sl3);
+            load_stage(&ring[sl4], o1, x1);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(sl2, o2, x2);
+            lds_barrier();
+            sl0 = sl3;
+        }
+    }
+    if (cur >= 0 && cnt > 0) flush(cur);
+    // store the block where it belongs to S (hi and lo of each FP64 sum)
+    const int col = 16 * cb + lr;
+    const int kc = col / sc, jj = col - kc * sc;
+    if (kc >= ngc) return;
+    const int ncl = sel4(kc & 3, nc0, nc1, nc2, nc3);
+    if (jj >= ncl) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rb + 4 * lk + r;
+        const int kr = row / sr, ii = row - kr * sr;
+        if (kr >= ngr) continue;
+        const int nr = sel4(kr & 3, nr0, nr1, nr2, nr3);
+        const int t = g.unit_out[u * 16 + kr * 4 + kc];
+        if (t >= 0 && ii < nr) {
+            const int64_t e = g.tile_off[t] + (int64_t)jj * nr + ii;
+            const float hi = (float)acc[r];
+            C[e] = hi;
+            C[ns + e] = (float)(acc[r] - (double)hi);
+        }
+    }
+}
+
 // Y = A X for an S-matrix A (tile layout) and a dense block X of r columns (column-major,
 // leading dimension n, basis order), the product behind the paper's error estimator
 // e_F (Section 5.1).  The tiles of block row nu are stored one after the other, so the
@@ -1816,6 +2276,18 @@ GemmArgs gemm_args(spm_pattern p)
 
 bool valid_prec(int prec) { return prec == SPM_F64 || prec == SPM_F32SPLIT || prec == SPM_F32ACC; }
 
+// The split-precision product runs on the matrix cores when the pattern was planned with
+// cluster levels, every cluster size is even (k pairs never straddle two clusters) and
+// every unit class has at most 7 blocks of 16 rows on a side; otherwise on the per-tile
+// compensated kernel.
+bool oz_ok(spm_pattern p)
+{
+    if (p->clevel.empty() || !p->all_even || p->nlev > 64) return false;
+    for (const auto &L : p->launches)
+        if (L.rb > 7 || L.cb > 7) return false;
+    return true;
+}
+
 size_t value_bytes(spm_pattern p, int prec)
 {
     return (size_t)p->n_stored * (prec == SPM_F64 ? 8 : prec == SPM_F32SPLIT ? 8 : 4);
@@ -1976,9 +2448,15 @@ bool f32acc_grouped(spm_pattern p)
 // Workspace of one product C = P_S(op(A) op(B)): the grouped kernels compute
 // P_S(A' B'^T) with A' = op(A) and B'^T = op(B), so A is transposed into the
 // workspace when op(A) = A^T and B when op(B) = B.
+size_t oz_ws_bytes(spm_pattern p)
+{
+    return 2 * ws_align((size_t)p->n_stored * 8) + 2 * ws_align((size_t)p->n * p->nlev * sizeof(int32_t));
+}
+
 size_t gemm_ws_bytes(spm_pattern p, int prec, int ta, int tb)
 {
     if (p->n_tiles == 0) return 0;
+    if (prec == SPM_F32SPLIT && oz_ok(p)) return oz_ws_bytes(p);
     size_t el;
     if (prec == SPM_F64) el = sizeof(double);
     else if (prec == SPM_F32ACC && f32acc_grouped(p)) el = sizeof(float);
@@ -2054,6 +2532,66 @@ int gemm_f32acc_ws(spm_pattern p, const float *A, int ta, const float *B, int tb
     return st;
 }
 
+// F32SPLIT on the matrix cores: slices of op(A) (rows) and of op(B)^T (columns of op(B))
+// with their per-row-and-level exponents in ws, then one launch per unit class.
+int gemm_oz_ws(spm_pattern p, const float *A, int ta, const float *B, int tb, float *C, char *ws, hipStream_t s)
+{
+    const size_t sb = ws_align((size_t)p->n_stored * 8), eb = ws_align((size_t)p->n * p->nlev * sizeof(int32_t));
+    uint4 *SA = reinterpret_cast<uint4 *>(ws), *SB = reinterpret_cast<uint4 *>(ws + sb);
+    int32_t *EA = reinterpret_cast<int32_t *>(ws + 2 * sb), *EB = reinterpret_cast<int32_t *>(ws + 2 * sb + eb);
+    const size_t slds = (size_t)kMax * p->nlev * sizeof(int);
+    // view of op(A): rows of A (ta = 0, strided in the tiles) or columns of A (ta = 1);
+    // view of op(B)^T: columns of B (tb = 0, contiguous) or rows of B (tb = 1)
+    hipLaunchKernelGGL(k_oz_slice, dim3((unsigned)p->nc), dim3(64 * kSliceWaves), slds, s, p->nc, p->nlev, ta ? 1 : 0,
+                       p->n_stored, p->d_blk_rp.ptr, p->d_tile_col.ptr, p->d_tile_off.ptr, p->d_trans.ptr,
+                       p->d_nfun.ptr, p->d_cstart.ptr, p->d_clevel.ptr, A, SA, EA);
+    hipLaunchKernelGGL(k_oz_slice, dim3((unsigned)p->nc), dim3(64 * kSliceWaves), slds, s, p->nc, p->nlev, tb ? 0 : 1,
+                       p->n_stored, p->d_blk_rp.ptr, p->d_tile_col.ptr, p->d_tile_off.ptr, p->d_trans.ptr,
+                       p->d_nfun.ptr, p->d_cstart.ptr, p->d_clevel.ptr, B, SB, EB);
+    SPM_HIP(hipGetLastError());
+    GroupArgs g;
+    g.grp_mem = p->d_grp_mem.ptr; g.grp_s = p->d_grp_s.ptr; g.grp_g = p->d_grp_g.ptr;
+    g.unit_gr = p->d_unit_gr.ptr; g.unit_gc = p->d_unit_gc.ptr; g.unit_out = p->d_unit_out.ptr;
+    g.unit_order = p->d_unit_order.ptr; g.pair_off = p->d_pair_off.ptr; g.pair_a = p->d_pair_a_lv.ptr;
+    g.pair_b = p->d_pair_b_lv.ptr; g.gl_nm = p->d_gl_nml.ptr; g.gl_offd = p->d_gl_offT.ptr;
+    g.stage_off = p->d_stage_off_lv.ptr; g.stage_first = p->d_stage_first_lv.ptr; g.tile_off = p->d_tile_off.ptr;
+    g.nfun = p->d_nfun.ptr;
+    g.lxa = g.lxb = 4;
+    g.WR = g.WC = g.nsplit = 1;
+    OzArgs z{EA, EB, p->d_cstart.ptr, p->nlev};
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> ready;   // (device, kernel)
+    int dev = 0;
+    SPM_HIP(hipGetDevice(&dev));
+    for (const auto &L : p->launches) {
+        g.first = L.first;
+        g.count = L.count;
+        g.RB = L.rb;
+        g.CB = L.cb;
+        const int rows_split = L.rb > 1 && L.cb == 1 ? 1 : 0;
+        const int sub_rows = L.rb > 1 && L.cb > 1 ? L.rb : 1;
+        const int nconsumer = rows_split ? L.rb : L.cb;
+        const int erows = rows_split ? 16 * L.rb : 16, ecols = rows_split ? 16 : 16 * L.cb;
+        const bool share = nconsumer > 1;
+        const size_t lds = (share ? ring_bytes<5, OzTab>() + 6 * 4096 : ring_bytes<3, OzTab>()) +
+                           (size_t)(erows + ecols) * p->nlev * sizeof(int);
+        const void *k = share ? (const void *)k_mgemm_oz<8, true> : (const void *)k_mgemm_oz<2, false>;
+        const int threads = share ? 512 : 128;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            if (!ready.count({dev, k})) {
+                SPM_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+                ready.insert({dev, k});
+            }
+        }
+        const int64_t nwg = sub_rows > 1 ? (L.count + 7) / 8 * 8 * sub_rows : L.count;
+        const int64_t ns = p->n_stored;
+        void *args[] = {&g, &z, (void *)&rows_split, (void *)&sub_rows, &SA, &SB, &C, (void *)&ns};
+        SPM_HIP(hipLaunchKernel(k, dim3((unsigned)nwg), dim3(threads), args, lds, s));
+    }
+    return SPM_OK;
+}
+
 // C = P_S(op(A) op(B)) in precision prec with a workspace of at least
 // gemm_ws_bytes(p, prec, ta, tb) bytes (256-byte aligned).
 int gemm_ws(spm_pattern p, int prec, const void *A, int ta, const void *B, int tb, void *C, void *ws,
@@ -2068,6 +2606,9 @@ int gemm_ws(spm_pattern p, int prec, const void *A, int ta, const void *B, int t
     } else if (prec == SPM_F32ACC && f32acc_grouped(p)) {
         st = gemm_f32acc_ws(p, static_cast<const float *>(A), ta, static_cast<const float *>(B), tb,
                             static_cast<float *>(C), w, s);
+    } else if (prec == SPM_F32SPLIT && oz_ok(p)) {
+        st = gemm_oz_ws(p, static_cast<const float *>(A), ta, static_cast<const float *>(B), tb,
+                        static_cast<float *>(C), w, s);
     } else {
         GemmArgs g = gemm_args(p);
         dim3 grid((unsigned)p->n_tiles), block(64);

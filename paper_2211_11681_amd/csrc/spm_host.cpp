@@ -526,6 +526,8 @@ void build_groups(spm_pattern_s *p)
     for (int64_t u = 0; u < nu; ++u) p->pair_off[u + 1] = p->pair_off[u] + cnt[u];
     p->pair_a.resize(p->pair_off[nu]);
     p->pair_b.resize(p->pair_off[nu]);
+    p->pair_a_lv.assign(!p->clevel.empty() ? p->pair_off[nu] : 0, 0);
+    p->pair_b_lv.assign(!p->clevel.empty() ? p->pair_off[nu] : 0, 0);
     // Order of a unit's middle clusters (the sum over mu may run in any order).  Both
     // kernels skip work per stage: the register-direct one a 16-column (or 16-row) block
     // of the wide side none of whose members has a tile in the stage, the staged one a
@@ -534,9 +536,11 @@ void build_groups(spm_pattern_s *p)
     // block has work).  Inside a group they go largest first, each stage topped up from
     // the small end while its 32 k rows and 8 clusters allow (a 28-function leaf shares
     // its stage with a 4-function cluster instead of leaving 4 rows empty).
-    struct Item { int32_t key, size; int64_t q; };
+    struct Item { int32_t key, size, level; int64_t q; };
+    const bool lev = !p->clevel.empty();
+    // by_level: inside a key group, level by level (finest first), topped up within a level
     auto reorder = [&](int64_t u, int32_t *pa, int32_t *pb, int64_t np, std::vector<Item> &it,
-                       std::vector<int32_t> &tmp) {
+                       std::vector<int32_t> &tmp, bool by_level) {
         if (np < 2) return;
         const bool wide_c = p->grp_R[p->unit_gc[u]] > 16, wide_r = p->grp_R[p->unit_gr[u]] > 16;
         it.resize(np);
@@ -546,15 +550,18 @@ void build_groups(spm_pattern_s *p)
                 if (wide_r) key |= (p->gl_tile[(int64_t)pa[q] * 4 + k] >= 0 ? 1 : 0) << (4 + k);
                 if (wide_c) key |= (p->gl_tile[(int64_t)pb[q] * 4 + k] >= 0 ? 1 : 0) << k;
             }
-            it[q] = {key, p->nfun[p->gl_mu[pa[q]]], q};
+            const int32_t mu = p->gl_mu[pa[q]];
+            it[q] = {key, p->nfun[mu], by_level ? p->clevel[mu] : 0, q};
         }
         std::stable_sort(it.begin(), it.end(), [](const Item &x, const Item &y) {
-            return x.key != y.key ? x.key < y.key : x.size > y.size;
+            if (x.key != y.key) return x.key < y.key;
+            if (x.level != y.level) return x.level > y.level;
+            return x.size > y.size;
         });
         tmp.clear();
         for (int64_t g0 = 0; g0 < np;) {
             int64_t g1 = g0;
-            while (g1 < np && it[g1].key == it[g0].key) ++g1;
+            while (g1 < np && it[g1].key == it[g0].key && it[g1].level == it[g0].level) ++g1;
             int64_t i = g0, j = g1 - 1;
             while (i <= j) {
                 int kacc = it[i].size, n = 1;
@@ -581,7 +588,13 @@ void build_groups(spm_pattern_s *p)
                 for (int64_t u = w; u < nu; u += nth) {
                     int32_t *pa = p->pair_a.data() + p->pair_off[u], *pb = p->pair_b.data() + p->pair_off[u];
                     merge(u, pa, pb);
-                    reorder(u, pa, pb, cnt[u], it, tmp);
+                    if (lev) {
+                        int32_t *qa = p->pair_a_lv.data() + p->pair_off[u], *qb = p->pair_b_lv.data() + p->pair_off[u];
+                        std::copy(pa, pa + cnt[u], qa);
+                        std::copy(pb, pb + cnt[u], qb);
+                        reorder(u, qa, qb, cnt[u], it, tmp, true);
+                    }
+                    reorder(u, pa, pb, cnt[u], it, tmp, false);
                 }
             });
         for (auto &x : th) x.join();
@@ -592,23 +605,35 @@ void build_groups(spm_pattern_s *p)
     const int64_t ne = (int64_t)p->gl_mu.size();
     p->gl_nm.resize(ne);
     p->gl_offd.assign(ne * 4 + 4, -1);   // padded: 16-byte reads of the last entry stay in bounds
+    if (lev) {
+        p->gl_nml.resize(ne);
+        p->gl_offT.assign(ne * 4 + 4, -1);
+    }
     for (int64_t e = 0; e < ne; ++e) {
         p->gl_nm[e] = p->nfun[p->gl_mu[e]];
+        if (lev) p->gl_nml[e] = p->gl_nm[e] | p->clevel[p->gl_mu[e]] << 8;
         for (int k = 0; k < 4; ++k) {
             const int32_t t = p->gl_tile[e * 4 + k];
             if (t >= 0) p->gl_offd[e * 4 + k] = p->tile_off[t];
+            if (t >= 0 && lev) p->gl_offT[e * 4 + k] = p->tile_off[p->trans[t]];
         }
     }
     // stages: consecutive middle clusters of a unit packed while their sizes sum to at most
-    // 32 k rows (a cluster may start at any row; only the stage's last k step is padded)
+    // 32 k rows (a cluster may start at any row; only the stage's last k step is padded).
+    // With levels a second list of stages (by_level) holds clusters of one level each, for
+    // the split-precision product; the FP64 and FP32 stages may span two levels.
     std::vector<int64_t> nst(nu, 0);
-    auto pack = [&](int64_t u, int32_t *out) {
+    auto pack_list = [&](int64_t u, int32_t *out, bool by_level) {
         int64_t ns = 0;
         int kacc = 0, np = 0;
         const int64_t f0 = p->pair_off[u], f1 = p->pair_off[u + 1];
+        int lv = -1;
+        const int32_t *pa = by_level ? p->pair_a_lv.data() : p->pair_a.data();
         for (int64_t f = f0; f < f1; ++f) {
-            const int km = p->gl_nm[p->pair_a[f]];
-            if (np == 0 || kacc + km > 32 || np == 8) {
+            const int km = p->gl_nm[pa[f]];
+            const int lf = by_level ? p->clevel[p->gl_mu[pa[f]]] : 0;
+            if (np == 0 || kacc + km > 32 || np == 8 || lf != lv) {
+                lv = lf;
                 if (out) out[ns] = (int32_t)(f - f0);
                 ++ns;
                 kacc = 0;
@@ -617,28 +642,39 @@ void build_groups(spm_pattern_s *p)
             kacc += km;
             ++np;
         }
-        // an even stage count: the register-direct kernels run two stages per loop trip
-        // with a single exit; the extra stage is empty (it starts at the end of the list)
-        if (ns & 1) {
+        // a stage count that is a multiple of the kernels' loop trip (two stages for the
+        // FP64 and FP32 kernels, two or three for the split-precision ones), so that the
+        // loops have a single exit; the extra stages are empty (they start at the end of the
+        // list)
+        const int mult = by_level ? 6 : 2;
+        while (ns % mult) {
             if (out) out[ns] = (int32_t)(f1 - f0);
             ++ns;
         }
         nst[u] = ns;
     };
-    {
+    auto pack_all = [&](bool by_level, std::vector<int64_t> &off, std::vector<int32_t> &first) {
+        {
+            std::vector<std::thread> th;
+            for (unsigned w = 0; w < nth; ++w)
+                th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) pack_list(u, nullptr, by_level); });
+            for (auto &x : th) x.join();
+        }
+        off.assign(nu + 1, 0);
+        for (int64_t u = 0; u < nu; ++u) off[u + 1] = off[u] + nst[u];
+        first.resize(off[nu]);
         std::vector<std::thread> th;
         for (unsigned w = 0; w < nth; ++w)
-            th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) pack(u, nullptr); });
+            th.emplace_back([&, w]() {
+                for (int64_t u = w; u < nu; u += nth) pack_list(u, first.data() + off[u], by_level);
+            });
         for (auto &x : th) x.join();
-    }
-    p->stage_off.assign(nu + 1, 0);
-    for (int64_t u = 0; u < nu; ++u) p->stage_off[u + 1] = p->stage_off[u] + nst[u];
-    p->stage_first.resize(p->stage_off[nu]);
-    {
-        std::vector<std::thread> th;
-        for (unsigned w = 0; w < nth; ++w)
-            th.emplace_back([&, w]() { for (int64_t u = w; u < nu; u += nth) pack(u, p->stage_first.data() + p->stage_off[u]); });
-        for (auto &x : th) x.join();
+    };
+    pack_all(false, p->stage_off, p->stage_first);
+    if (lev) pack_all(true, p->stage_off_lv, p->stage_first_lv);
+    else {
+        p->stage_off_lv.clear();
+        p->stage_first_lv.clear();
     }
     // Launch classes by (row blocks, column blocks).  Inside a class the units are cut
     // into strips that share one operand group: the column group when the columns are
@@ -840,8 +876,26 @@ void build_layout(spm_pattern_s *p)
 
 }  // namespace
 
+// Levels of the clusters (optional): every value in [0, 64).
+static int check_levels(int32_t nc, const int32_t *lev)
+{
+    if (!lev) return SPM_OK;
+    for (int32_t c = 0; c < nc; ++c)
+        if (lev[c] < 0 || lev[c] >= 64) return fail(SPM_EINVAL, "cluster level out of [0, 64)");
+    return SPM_OK;
+}
+
+static void set_levels(spm_pattern_s *p, const int32_t *lev)
+{
+    p->clevel.clear();
+    p->nlev = 0;
+    if (!lev) return;
+    p->clevel.assign(lev, lev + p->nc);
+    for (int32_t c = 0; c < p->nc; ++c) p->nlev = std::max(p->nlev, lev[c] + 1);
+}
+
 extern "C" int spm_block_pattern_plan(int64_t n, int32_t nc, const int64_t *cs, const int64_t *brp,
-                                      const int32_t *bcol, spm_pattern *out)
+                                      const int32_t *bcol, const int32_t *lev, spm_pattern *out)
 {
     if (!cs || !brp || !bcol || !out) return fail(SPM_EINVAL, "spm_block_pattern_plan: null pointer");
     if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_block_pattern_plan: bad n");
@@ -849,6 +903,7 @@ extern "C" int spm_block_pattern_plan(int64_t n, int32_t nc, const int64_t *cs, 
     int st = check_clusters(n, nc, cs);
     if (st) return st;
     if ((st = check_csr(nc, nc, brp, bcol, "block pattern"))) return st;
+    if ((st = check_levels(nc, lev))) return st;
     std::vector<int32_t> nf(nc);
     for (int c = 0; c < nc; ++c) nf[c] = (int32_t)(cs[c + 1] - cs[c]);
     if ((st = check_symmetric_diag(nc, brp, bcol, &nf, "block pattern"))) return st;
@@ -867,6 +922,7 @@ extern "C" int spm_block_pattern_plan(int64_t n, int32_t nc, const int64_t *cs, 
                     if (nf[bcol[e]] > 0) p->tile_col.push_back(bcol[e]);
             p->blk_rp[r + 1] = (int64_t)p->tile_col.size();
         }
+        set_levels(p, lev);
         build_layout(p);
         p->nnz = p->n_stored;
         p->masked = false;
@@ -879,7 +935,7 @@ extern "C" int spm_block_pattern_plan(int64_t n, int32_t nc, const int64_t *cs, 
 }
 
 extern "C" int spm_compress_pattern_plan(int64_t n, const int64_t *rp, const int32_t *col, int32_t nc,
-                                         const int64_t *cs, spm_pattern *out)
+                                         const int64_t *cs, const int32_t *lev, spm_pattern *out)
 {
     if (!rp || !col || !cs || !out) return fail(SPM_EINVAL, "spm_compress_pattern_plan: null pointer");
     if (n < 1 || n > INT32_MAX) return fail(SPM_EINVAL, "spm_compress_pattern_plan: bad n");
@@ -888,6 +944,7 @@ extern "C" int spm_compress_pattern_plan(int64_t n, const int64_t *rp, const int
     if (st) return st;
     if ((st = check_csr(n, n, rp, col, "pattern"))) return st;
     if ((st = check_symmetric_diag(n, rp, col, nullptr, "pattern"))) return st;
+    if ((st = check_levels(nc, lev))) return st;
     spm_pattern_s *p = new (std::nothrow) spm_pattern_s;
     if (!p) return fail(SPM_ENOMEM, "host allocation");
     try {
@@ -913,6 +970,7 @@ extern "C" int spm_compress_pattern_plan(int64_t n, const int64_t *rp, const int
             p->blk_rp[r + 1] = (int64_t)p->tile_col.size();
         }
         if (p->blk_rp[nc] > INT32_MAX) { delete p; return fail(SPM_EUNSUPPORTED, "more than 2^31-1 tiles"); }
+        set_levels(p, lev);
         build_layout(p);
         p->nnz = rp[n];
         p->csr_rp.assign(rp, rp + n + 1);
@@ -957,7 +1015,7 @@ extern "C" int spm_block_pattern_upload(int64_t n, int32_t nc, const int64_t *cs
                                         const int32_t *bcol, void *stream, spm_pattern *out)
 {
     if (!out) return fail(SPM_EINVAL, "spm_block_pattern_upload: null pointer");
-    const int st = spm_block_pattern_plan(n, nc, cs, brp, bcol, out);
+    const int st = spm_block_pattern_plan(n, nc, cs, brp, bcol, nullptr, out);
     return st ? st : upload_owned(*out, stream, out);
 }
 
@@ -965,8 +1023,17 @@ extern "C" int spm_compress_pattern_upload(int64_t n, const int64_t *rp, const i
                                            const int64_t *cs, void *stream, spm_pattern *out)
 {
     if (!out) return fail(SPM_EINVAL, "spm_compress_pattern_upload: null pointer");
-    const int st = spm_compress_pattern_plan(n, rp, col, nc, cs, out);
+    const int st = spm_compress_pattern_plan(n, rp, col, nc, cs, nullptr, out);
     return st ? st : upload_owned(*out, stream, out);
+}
+
+extern "C" int spm_pattern_upload(spm_pattern p, void *stream)
+{
+    if (!p) return fail(SPM_EINVAL, "spm_pattern_upload: null pattern");
+    if (p->uploaded) return fail(SPM_EINVAL, "spm_pattern_upload: pattern already uploaded");
+    int st = spm::upload_pattern_device(p, nullptr, 0, (hipStream_t)stream);
+    if (st) spm::free_pattern_device(p);
+    return st;
 }
 
 extern "C" int spm_pattern_workspace_bytes(spm_pattern p, size_t *bytes)

@@ -130,6 +130,18 @@ struct spm_pattern_s {
         double padded_macs;       // multiply-adds the kernels issue for it before block skipping
     };
     std::vector<Launch> launches;
+    // tree levels of the clusters (optional, given at planning): with them the middle
+    // clusters of a unit are ordered level by level and no stage mixes two levels, as the
+    // split-precision product scales its operands per row and level
+    std::vector<int32_t> clevel;      // nc, or empty
+    int32_t nlev = 0;                 // 1 + largest level (0 without levels)
+    std::vector<int32_t> gl_nml;      // entries: functions | level << 8 of the entry's cluster
+    std::vector<int64_t> gl_offT;     // entries x 4: element offset of tile (mu, member), -1 absent
+    // the middle clusters of each unit once more, ordered level by level, and stages of one
+    // level each (the split-precision product; the FP64 and FP32 order is kept as it is)
+    std::vector<int32_t> pair_a_lv, pair_b_lv;
+    std::vector<int64_t> stage_off_lv;    // units + 1
+    std::vector<int32_t> stage_first_lv;  // first pair of each stage (relative to the unit's pair_off)
     double padded_macs = 0.0;         // multiply-adds the grouped kernel issues (incl. padding)
     bool all_even = false;            // every cluster owns an even number of functions
     bool all_mult4 = false;           // every cluster owns a multiple of 4 functions
@@ -151,6 +163,8 @@ struct spm_pattern_s {
         d_unit_order;
     spm::DevBuf<int64_t> d_gl_rp, d_pair_off, d_gl_offd, d_stage_off;
     spm::DevBuf<int32_t> d_pair_a, d_pair_b, d_gl_nm, d_stage_first;
+    spm::DevBuf<int32_t> d_clevel, d_gl_nml, d_stage_first_lv, d_pair_a_lv, d_pair_b_lv;
+    spm::DevBuf<int64_t> d_gl_offT, d_stage_off_lv;
     spm::DevBuf<uint8_t> d_keep;      // n_stored, masked patterns only
     spm::DevBuf<double> d_partial;    // reduction partials
 };

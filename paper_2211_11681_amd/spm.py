@@ -129,27 +129,38 @@ class Pattern:
 
     @classmethod
     def from_tree(cls, tree: Tree, eta: float):
+        """Block pattern of the tree, planned with the clusters' levels and uploaded."""
         rp, col = tree.block_pattern(eta)
-        return cls.from_blocks(tree.n, tree.arrays()["cluster_start"], rp, col)
+        arr = tree.arrays()
+        pat = cls.plan_blocks(tree.n, arr["cluster_start"], rp, col, levels=arr["level"])
+        pat.upload()
+        return pat
 
     @classmethod
-    def plan_blocks(cls, n, cluster_start, blk_row_ptr, blk_col):
-        """Host-only planning (no device memory); upload with upload_workspace()."""
+    def plan_blocks(cls, n, cluster_start, blk_row_ptr, blk_col, levels=None):
+        """Host-only planning (no device memory); upload with upload() or upload_workspace()."""
         cs = _host(cluster_start, np.int64)
         rp = _host(blk_row_ptr, np.int64)
         col = _host(blk_col, np.int32)
+        lev = None if levels is None else _host(levels, np.int32)
         h = ctypes.c_void_p()
-        call("spm_block_pattern_plan", n, len(cs) - 1, _ptr(cs), _ptr(rp), _ptr(col), ctypes.byref(h))
+        call("spm_block_pattern_plan", n, len(cs) - 1, _ptr(cs), _ptr(rp), _ptr(col), _ptr(lev), ctypes.byref(h))
         return cls(h, n, len(cs) - 1)
 
     @classmethod
-    def plan_csr(cls, n, row_ptr, col_idx, cluster_start):
+    def plan_csr(cls, n, row_ptr, col_idx, cluster_start, levels=None):
         rp = _host(row_ptr, np.int64)
         col = _host(col_idx, np.int32)
         cs = _host(cluster_start, np.int64)
+        lev = None if levels is None else _host(levels, np.int32)
         h = ctypes.c_void_p()
-        call("spm_compress_pattern_plan", n, _ptr(rp), _ptr(col), len(cs) - 1, _ptr(cs), ctypes.byref(h))
+        call("spm_compress_pattern_plan", n, _ptr(rp), _ptr(col), len(cs) - 1, _ptr(cs), _ptr(lev), ctypes.byref(h))
         return cls(h, n, len(cs) - 1)
+
+    def upload(self):
+        """Uploads the device tables into a block the library allocates."""
+        call("spm_pattern_upload", self._h, _stream())
+        return self
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
