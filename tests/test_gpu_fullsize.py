@@ -20,8 +20,9 @@ vectors against the oracle rows (tolerance 1e-12 * ||K_i|| ||X||), and the fast
 samplet transform of X against the oracle's sparse T at every entry (1e-12 * ||X||).
 
 It also certifies the masked Newton-Schulz inverse of A = K^eta + 1e-2 I at this
-size, 20 iterations all in FP64 and in the recipe of the inverse benchmark (the
-first 17 in F32ACC, the last 3 in FP64): for the sampled pairs (i, j) in S the
+size, 20 iterations all in FP64 and in the recipes of the inverse benchmark (the
+first 17 in F32ACC or in the FP32-split product on matrix cores, the last 3 in
+FP64): for the sampled pairs (i, j) in S the
 residual entry delta_ij - sum_{k in S_i cap S_j} A_ik X_kj, with the oracle's rows
 of A and the library's X, must vanish to 1e-10 of sum_k |A_ik X_kj| (the converged
 iteration has P_S(A X) = I on S; a wrong iterate leaves residuals of order 1).
@@ -147,7 +148,7 @@ def test_product_full_size_sampled_entries():
         assert np.all(tkey[t_] == ci * nc + cj)
         return to[t_] + (j - cs[cj]) * nf[ci] + (ii - cs[ci])
 
-    for bulk, nfin in (("f64", 20), ("f32acc", 3)):
+    for bulk, nfin in (("f64", 20), ("f32acc", 3), ("f32split", 3)):
         print(f"case: Newton-Schulz 20 iterations, bulk {bulk}, last {nfin} in FP64", flush=True)
         Xns, res, _ = spm.newton_schulz(pat, A, 20, nfin, bulk, 2.0 / (1.0 + 2.0 * mu))
         worst = 0.0
