@@ -44,10 +44,14 @@ void for_each_table(spm_pattern_s *p, F &&f)
     f(p->d_stage_off, p->stage_off); f(p->d_stage_first, p->stage_first); f(p->d_csr_pos, p->csr_pos);
     f(p->d_clevel, p->clevel); f(p->d_gl_nml, p->gl_nml); f(p->d_gl_offT, p->gl_offT);
     f(p->d_stage_off_lv, p->stage_off_lv); f(p->d_stage_first_lv, p->stage_first_lv);
-    f(p->d_pair_a_lv, p->pair_a_lv); f(p->d_pair_b_lv, p->pair_b_lv);
+    f(p->d_pair_a_lv, p->pair_a_lv); f(p->d_pair_b_lv, p->pair_b_lv); f(p->d_diag_pos, p->diag_pos);
 }
 
-int64_t partial_count(const spm_pattern_s *p) { return (p->n_tiles + kRedTiles - 1) / kRedTiles + 1; }
+static constexpr int kFlatBlocks = 2048;  // fixed grid of the flat reductions (so a fixed summation order)
+int64_t partial_count(const spm_pattern_s *p)
+{
+    return std::max<int64_t>((p->n_tiles + kRedTiles - 1) / kRedTiles + 1, kFlatBlocks);
+}
 
 }  // namespace
 
@@ -257,6 +261,80 @@ __global__ __launch_bounds__(256) void k_reduce_tiles(int op, int64_t n_tiles, c
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Sum of squares, squared distance and dot product over the stored entries in storage
+// order, as one coalesced pass: workgroup b owns a fixed contiguous range of 4096-entry
+// segments, and each thread sums entries tid + 256 k of each segment.  For
+// sum (alpha I - X)^2 the diagonal entries of the segment are marked in an LDS bitmap
+// from the ascending list of diagonal positions (the list pointer only moves forward).
+constexpr int kFlatSeg = 4096;
+template <int PREC, int OP>
+__global__ __launch_bounds__(256) void k_reduce_flat(int64_t ns, const void *x, const void *y,
+                                                     const int64_t *__restrict__ diag, int64_t ndiag,
+                                                     double alpha, double *partial)
+{
+    __shared__ double red[256];
+    __shared__ uint32_t mark[kFlatSeg / 32];
+    const int tid = threadIdx.x;
+    const int64_t nseg = (ns + kFlatSeg - 1) / kFlatSeg;
+    const int64_t per = (nseg + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min(nseg, g0 + per);
+    double acc = 0.0;
+    int64_t q = 0;
+    if (OP == RED_SQDIST_EYE && g0 < g1) {
+        int64_t lo = 0, hi = ndiag;                       // first diagonal position >= segment g0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (diag[mid] < g0 * kFlatSeg) lo = mid + 1;
+            else hi = mid;
+        }
+        q = lo;
+    }
+    for (int64_t g = g0; g < g1; ++g) {
+        const int64_t a = g * kFlatSeg;
+        if (OP == RED_SQDIST_EYE) {
+            for (int w = tid; w < kFlatSeg / 32; w += 256) mark[w] = 0;
+            __syncthreads();
+            for (;;) {
+                const int64_t qq = q + tid;
+                const bool in = qq < ndiag && diag[qq] < a + kFlatSeg;
+                if (in) {
+                    const int o = (int)(diag[qq] - a);
+                    atomicOr(&mark[o >> 5], 1u << (o & 31));
+                }
+                const int cnt = __syncthreads_count(in);
+                q += cnt;
+                if (cnt < 256) break;
+            }
+        }
+        double xv[16], yv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t e = a + tid + 256 * k;
+            xv[k] = e < ns ? load_val(PREC, x, e, ns) : 0.0;
+            yv[k] = ((OP == RED_SQDIST && y) || OP == RED_DOT) && e < ns ? load_val(PREC, y, e, ns) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int o = tid + 256 * k;
+            if (OP == RED_DOT) {
+                acc += xv[k] * yv[k];
+            } else {
+                double d = xv[k] - yv[k];
+                if (OP == RED_SQDIST_EYE && (mark[o >> 5] >> (o & 31) & 1u)) d = alpha - xv[k];
+                acc += d * d;
+            }
+        }
+        if (OP == RED_SQDIST_EYE) __syncthreads();     // the bitmap is cleared for the next segment
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) partial[blockIdx.x] = red[0];
 }
 
 // out = post(sum of partials); post: 0 = identity, 1 = sqrt(s) * scale
@@ -2239,6 +2317,10 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void k_spmm(int32_t nc, int64_t n,
     }
 }
 
+// out = the tiles of in, each transposed into the place of its mirror tile.  One wavefront
+// per tile, two tiles in flight per wavefront: the output entries are written in order
+// (coalesced) and gathered from the input tile (at most 32 x 32 entries, so a wavefront's
+// gathers stay inside a few cache lines of one small tile).
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
                                                    const int32_t *__restrict__ tile_row,
@@ -2246,21 +2328,52 @@ __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_
                                                    const int32_t *__restrict__ trans, const int32_t *__restrict__ nfun,
                                                    const T *__restrict__ in, T *__restrict__ out)
 {
-    __shared__ T sh[32 * 33];
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int nr = nfun[tile_row[t]], nc = nfun[tile_col[t]];
-        const T *src = in + tile_off[t];                 // (i, j) at j * nr + i
-        T *dst = out + tile_off[trans[t]];               // (j, i) at i * nc + j
-        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
-            const int j = e / nr, i = e - j * nr;
-            sh[i * 33 + j] = src[e];
+    constexpr int kPer = kMax * kMax / 64;        // entries per lane of the largest tile
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t w0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t t = w0; t < n_tiles; t += 2 * nw) {
+        const int64_t u = t + nw;
+        int nr[2], nc[2];
+        int64_t so[2], dof[2];
+        nr[0] = nfun[tile_row[t]];
+        nc[0] = nfun[tile_col[t]];
+        so[0] = tile_off[t];
+        dof[0] = tile_off[trans[t]];
+        if (u < n_tiles) {
+            nr[1] = nfun[tile_row[u]];
+            nc[1] = nfun[tile_col[u]];
+            so[1] = tile_off[u];
+            dof[1] = tile_off[trans[u]];
+        } else {
+            nr[1] = nc[1] = 0;
+            so[1] = dof[1] = 0;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
-            const int i = e / nc, j = e - i * nc;
-            dst[e] = sh[i * 33 + j];
+        T v[2][kPer];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ne = nr[h] * nc[h];
+            // row i of the transposed tile from e / nc: (e + 1/2) / nc is at least 1/(2 nc) away
+            // from an integer, far more than the float error for e < 1024
+            const float rc = 1.0f / (float)max(nc[h], 1);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int e = lane + 64 * k;
+                if (e < ne) {
+                    const int i = (int)(((float)e + 0.5f) * rc), j = e - i * nc[h];
+                    v[h][k] = in[so[h] + (int64_t)j * nr[h] + i];
+                }
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ne = nr[h] * nc[h];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int e = lane + 64 * k;
+                if (e < ne) out[dof[h] + e] = v[h][k];
+            }
+        }
     }
 }
 
@@ -2428,7 +2541,7 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
 template <typename T>
 int launch_transpose(spm_pattern p, const T *in, T *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_transpose<T>, dim3(grid1d(p->n_tiles, 1, 1 << 20)), dim3(256), 0, s, p->n_tiles,
+    hipLaunchKernelGGL(k_transpose<T>, dim3(grid1d(p->n_tiles, 8, 16384)), dim3(256), 0, s, p->n_tiles,
                        p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_trans.ptr, p->d_nfun.ptr, in, out);
     SPM_HIP(hipGetLastError());
     return SPM_OK;
@@ -2652,10 +2765,30 @@ int launch_gemm(spm_pattern p, int prec, const void *A, int ta, const void *B, i
 int launch_reduce(spm_pattern p, int op, int prec, const void *x, const void *y, const double *vec, double alpha,
                   int post, double scale, double *out, hipStream_t s)
 {
-    const int64_t nb = std::max<int64_t>(1, (p->n_tiles + kRedTiles - 1) / kRedTiles);
-    hipLaunchKernelGGL(k_reduce_tiles, dim3((unsigned)nb), dim3(kRedThreads), 0, s, op, p->n_tiles,
-                       p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_nfun.ptr, p->d_cstart.ptr,
-                       prec, p->n_stored, x, y, vec, alpha, p->d_partial.ptr);
+    int64_t nb;
+    if (op == RED_QUAD) {
+        nb = std::max<int64_t>(1, (p->n_tiles + kRedTiles - 1) / kRedTiles);
+        hipLaunchKernelGGL(k_reduce_tiles, dim3((unsigned)nb), dim3(kRedThreads), 0, s, op, p->n_tiles,
+                           p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_nfun.ptr, p->d_cstart.ptr,
+                           prec, p->n_stored, x, y, vec, alpha, p->d_partial.ptr);
+    } else {
+        const int64_t ns = p->n_stored, nseg = (ns + kFlatSeg - 1) / kFlatSeg;
+        nb = std::max<int64_t>(1, std::min<int64_t>(kFlatBlocks, nseg));
+        const int64_t *dg = p->d_diag_pos.ptr;
+        const int64_t nd = (int64_t)p->d_diag_pos.n;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), 0, s, ns, x, y, dg, nd, alpha, p->d_partial.ptr);
+        };
+        auto by_op = [&](auto pc) {
+            constexpr int PC = decltype(pc)::value;
+            if (op == RED_SQDIST) go(k_reduce_flat<PC, RED_SQDIST>);
+            else if (op == RED_SQDIST_EYE) go(k_reduce_flat<PC, RED_SQDIST_EYE>);
+            else go(k_reduce_flat<PC, RED_DOT>);
+        };
+        if (prec == SPM_F64) by_op(std::integral_constant<int, SPM_F64>());
+        else if (prec == SPM_F32SPLIT) by_op(std::integral_constant<int, SPM_F32SPLIT>());
+        else by_op(std::integral_constant<int, SPM_F32ACC>());
+    }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, nb, p->d_partial.ptr, post, scale, out);
     SPM_HIP(hipGetLastError());
     return SPM_OK;

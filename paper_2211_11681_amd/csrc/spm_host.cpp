@@ -814,6 +814,12 @@ void build_layout(spm_pattern_s *p)
         base += len * p->nfun[r];
     }
     p->n_stored = p->tile_off[nt];
+    p->diag_pos.clear();
+    for (int r = 0; r < nc; ++r) {
+        const int64_t t = p->diag_tile[r];
+        if (t < 0) continue;
+        for (int i = 0; i < p->nfun[r]; ++i) p->diag_pos.push_back(p->tile_off[t] + (int64_t)i * (p->nfun[r] + 1));
+    }
     // pieces for the S x dense product
     p->pc_rp.assign(nc + 1, 0);
     p->pc_off.clear();

@@ -95,6 +95,7 @@ struct spm_pattern_s {
     std::vector<int64_t> blk_rp;      // nc + 1
     std::vector<int32_t> tile_row, tile_col, trans;   // n_tiles
     std::vector<int64_t> tile_off;    // n_tiles + 1
+    std::vector<int64_t> diag_pos;    // stored positions of the diagonal entries (of the diagonal tiles), ascending
     std::vector<int64_t> colprefix;   // n_tiles: entries of the tile row before this tile
     std::vector<int64_t> rowbase, rowlen;  // nc: CSR position of the block row's first entry, entries per row
     std::vector<int32_t> diag_tile;   // nc
@@ -166,6 +167,7 @@ struct spm_pattern_s {
     spm::DevBuf<int32_t> d_clevel, d_gl_nml, d_stage_first_lv, d_pair_a_lv, d_pair_b_lv;
     spm::DevBuf<int64_t> d_gl_offT, d_stage_off_lv;
     spm::DevBuf<uint8_t> d_keep;      // n_stored, masked patterns only
+    spm::DevBuf<int64_t> d_diag_pos;
     spm::DevBuf<double> d_partial;    // reduction partials
 };
 
