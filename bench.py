@@ -94,7 +94,7 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def cpu_baseline(ot, ob, eta, total_macs, nnz, threads, seed=77, clusters_per_level=3, tiles_per_cluster=64,
+def cpu_baseline(ot, ob, eta, total_macs, nnz, threads, seed=77, clusters_per_level=6, tiles_per_cluster=256,
                  tile_cap=None):
     """The oracle's sorted-merge product timed on the host over a level-stratified
     sample of output tiles, extrapolated to the whole product by exact multiply-adds.
@@ -135,7 +135,12 @@ def cpu_baseline(ot, ob, eta, total_macs, nnz, threads, seed=77, clusters_per_le
     if tile_cap is not None:
         tiles = tiles[:tile_cap]
     cols = sorted({c for _, c in tiles} - set(rows_of))
-    rows_of.update(pattern.block_rows(ot, eta, cols, diam))
+    # the block rows of the column clusters, in parallel slices (numpy releases the GIL)
+    from concurrent.futures import ThreadPoolExecutor
+    parts = [cols[k::threads] for k in range(threads) if cols[k::threads]]
+    with ThreadPoolExecutor(max_workers=max(1, len(parts))) as ex:
+        for r in ex.map(lambda part: pattern.block_rows(ot, eta, part, diam), parts):
+            rows_of.update(r)
     # entry-level CSR of the rows the sample reads: rows of nu (A) and of nu' (B^T)
     need = sorted({nu for nu, _ in tiles} | {c for _, c in tiles})
     n = int(cs[-1])
@@ -157,10 +162,9 @@ def cpu_baseline(ot, ob, eta, total_macs, nnz, threads, seed=77, clusters_per_le
         col[rp[cs[c]]:rp[cs[c + 1]]] = np.tile(colsof[c], int(nf[c]))
     # synthetic operand values in [-1, 1) (a fixed arithmetic sequence: the pattern, not
     # the values, sets the work of the merge)
-    idx = np.arange(rp[-1], dtype=np.int64)
-    a = (idx * 40503 % 65521) / 32760.5 - 1.0
-    bt = (idx * 30011 % 65519) / 32759.5 - 1.0
-    del idx
+    period_a, period_b = np.arange(65521, dtype=np.int64), np.arange(65519, dtype=np.int64)
+    a = np.resize((period_a * 40503 % 65521) / 32760.5 - 1.0, int(rp[-1]))      # a_e = f(e mod 65521)
+    bt = np.resize((period_b * 30011 % 65519) / 32759.5 - 1.0, int(rp[-1]))
     ii, jj, pos = [], [], []
     for nu, c in tiles:
         off = int(np.searchsorted(colsof[nu], cs[c]))           # first column of c in row nu's list
