@@ -2223,14 +2223,17 @@ __device__ __forceinline__ void spmm_mfma(int64_t q, int64_t p1, int nr, int64_t
             for (int k = 0; k < 4; ++k) red[16 * rb + 4 * k + lk][16 * cb + lr] = d[rb][cb][k];
 }
 
-template <int MAXR, int CB>
+// CL groups of 64 / CL column lanes: with CL = 4 each group takes 4 CB columns of X (16 CB
+// per pass, the four groups reading the same entries of A); with CL = 1 (at most four
+// columns of X) every lane reads its own column of A, so each entry is loaded once.
+template <int MAXR, int CB, int CL = 4>
 __device__ __forceinline__ void spmm_thin(int64_t q, int64_t p1, int nr, int64_t n, int r, int cc0,
                                           const int64_t *__restrict__ pc_off, const int64_t *__restrict__ pc_g,
                                           const int32_t *__restrict__ pc_w, const double *__restrict__ A,
                                           const double *__restrict__ X, double (*red)[16 * CB + 1])
 {
-    constexpr int M = 4 * CB;
-    const int lane = threadIdx.x & 63, jl = lane & 15, cl = lane >> 4;
+    constexpr int M = 4 * CB, JL = 64 / CL;
+    const int lane = threadIdx.x & 63, jl = lane % JL, cl = lane / JL;
     double acc[MAXR][M];
 #pragma unroll
     for (int i = 0; i < MAXR; ++i)
@@ -2244,16 +2247,16 @@ __device__ __forceinline__ void spmm_thin(int64_t q, int64_t p1, int nr, int64_t
         bool xon[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            xon[m] = cc0 + cl + 4 * m < r;
-            xr[m] = X + (int64_t)(cc0 + 4 * m) * n + g;
+            xon[m] = cc0 + cl + CL * m < r;
+            xr[m] = X + (int64_t)(cc0 + CL * m) * n + g;
         }
         const uint32_t xl = 8u * (uint32_t)(cl * n);
         constexpr int U = MAXR <= 4 ? 4 : 2;
-        for (int j0 = 0; j0 < w; j0 += 16 * U) {
+        for (int j0 = 0; j0 < w; j0 += JL * U) {
             double a[U][MAXR], x[U][M];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int jc = j0 + 16 * u + jl;
+                const int jc = j0 + JL * u + jl;
                 const bool jon = jc < w;
 #pragma unroll
                 for (int i = 0; i < MAXR; ++i)
@@ -2269,15 +2272,15 @@ __device__ __forceinline__ void spmm_thin(int64_t q, int64_t p1, int nr, int64_t
                     for (int m = 0; m < M; ++m) acc[i][m] = fma(a[u][i], x[u][m], acc[i][m]);
         }
     }
-    // fold the 16 column lanes of each X-column group (a fixed butterfly)
+    // fold the column lanes of each X-column group (a fixed butterfly)
 #pragma unroll
     for (int i = 0; i < MAXR; ++i)
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             double v = acc[i][m];
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-            if (jl == 0 && i < nr) red[i][cl + 4 * m] = v;
+            for (int o = 1; o < JL; o <<= 1) v += __shfl_xor(v, o, 64);
+            if (jl == 0 && i < nr) red[i][cl + CL * m] = v;
         }
 }
 
@@ -2300,7 +2303,9 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void k_spmm(int32_t nc, int64_t n,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t q0 = pc_rp[c] + wave, p1 = pc_rp[c + 1];
     for (int cc0 = 0; cc0 < r; cc0 += 16 * CB) {
-        if (nr <= 4) spmm_thin<4, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        if (nr <= 4 && r <= 4) spmm_thin<4, 1, 1>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        else if (nr <= 8 && r <= 4) spmm_thin<8, 1, 1>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
+        else if (nr <= 4) spmm_thin<4, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
         else if (nr <= 8) spmm_thin<8, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
         else if (nr <= 16) spmm_mfma<1, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
         else spmm_mfma<2, CB>(q0, p1, nr, n, r, cc0, pc_off, pc_g, pc_w, A, X, red[wave]);
@@ -2317,10 +2322,76 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void k_spmm(int32_t nc, int64_t n,
     }
 }
 
+// Raw buffer access (gfx9 resource word 3; byte offsets at or beyond the extent read 0 and
+// are not written).
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kBufOutside = 0x7fffffff;
+template <typename T> struct BufWord;
+template <> struct BufWord<double> { using type = unsigned long long; };
+template <> struct BufWord<float> { using type = unsigned; };
+template <typename T>
+__device__ inline typename BufWord<T>::type buf_load(__amdgpu_buffer_rsrc_t r, int off)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else
+        return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+template <typename T>
+__device__ inline void buf_store(__amdgpu_buffer_rsrc_t r, int off, typename BufWord<T>::type v)
+{
+    using u32x2 = __attribute__((ext_vector_type(2))) unsigned;
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+}
+
+// One pass of the transpose over two tiles with KP entries per lane (KP * 64 >= both sizes):
+// every access goes through the tile's own buffer resource, lanes past the end of a tile get
+// an offset beyond it (their loads return 0, their stores are dropped by the range check), so
+// the pass has no branch and each store waits only for its own load.  mid() runs between the
+// loads and the stores (the next pass's descriptors).
+template <typename T, int KP, typename Mid>
+__device__ inline void transpose_pass(int lane, const int (&nr)[2], const int (&nc)[2], const T *in,
+                                      const int64_t (&so)[2], T *out, const int64_t (&dof)[2], Mid mid)
+{
+    using Word = typename BufWord<T>::type;
+    Word v[2][KP];
+    __amdgpu_buffer_rsrc_t rout[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ne = nr[h] * nc[h];
+        const __amdgpu_buffer_rsrc_t rin =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(in + so[h]), 0, ne * (int)sizeof(T), kBufWord3);
+        rout[h] = __builtin_amdgcn_make_buffer_rsrc((void *)(out + dof[h]), 0, ne * (int)sizeof(T), kBufWord3);
+        // row i of the transposed tile from e / nc: (e + 1/2) / nc is at least 1/(2 nc) away
+        // from an integer, far more than the float error for e < 1024
+        const float rc = 1.0f / (float)max(nc[h], 1);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int e = lane + 64 * k;
+            const int i = (int)(((float)e + 0.5f) * rc), j = e - i * nc[h];
+            v[h][k] = buf_load<T>(rin, e < ne ? (j * nr[h] + i) * (int)sizeof(T) : kBufOutside);
+        }
+    }
+    mid();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ne = nr[h] * nc[h];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int e = lane + 64 * k;
+            buf_store<T>(rout[h], e < ne ? e * (int)sizeof(T) : kBufOutside, v[h][k]);
+        }
+    }
+}
+
 // out = the tiles of in, each transposed into the place of its mirror tile.  One wavefront
-// per tile, two tiles in flight per wavefront: the output entries are written in order
-// (coalesced) and gathered from the input tile (at most 32 x 32 entries, so a wavefront's
-// gathers stay inside a few cache lines of one small tile).
+// per tile, two tiles per pass: the output entries are written in order (coalesced) and
+// gathered from the input tile (at most 32 x 32 entries, so a wavefront's gathers stay
+// inside a few cache lines of one small tile).  The tile descriptors of the next pass are
+// loaded while the current pass's gathers are in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
                                                    const int32_t *__restrict__ tile_row,
@@ -2328,51 +2399,61 @@ __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_
                                                    const int32_t *__restrict__ trans, const int32_t *__restrict__ nfun,
                                                    const T *__restrict__ in, T *__restrict__ out)
 {
-    constexpr int kPer = kMax * kMax / 64;        // entries per lane of the largest tile
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
-    const int64_t w0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t t = w0; t < n_tiles; t += 2 * nw) {
-        const int64_t u = t + nw;
-        int nr[2], nc[2];
-        int64_t so[2], dof[2];
-        nr[0] = nfun[tile_row[t]];
-        nc[0] = nfun[tile_col[t]];
-        so[0] = tile_off[t];
-        dof[0] = tile_off[trans[t]];
-        if (u < n_tiles) {
-            nr[1] = nfun[tile_row[u]];
-            nc[1] = nfun[tile_col[u]];
-            so[1] = tile_off[u];
-            dof[1] = tile_off[trans[u]];
-        } else {
-            nr[1] = nc[1] = 0;
-            so[1] = dof[1] = 0;
+    int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // descriptors of the pass (tiles t and t + nw): sizes and input / output offsets
+    int nr[2] = {0, 0}, nc[2] = {0, 0};
+    int64_t so[2] = {0, 0}, dof[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t x = t + h * nw;
+        if (x < n_tiles) {
+            nr[h] = nfun[tile_row[x]];
+            nc[h] = nfun[tile_col[x]];
+            so[h] = tile_off[x];
+            dof[h] = tile_off[trans[x]];
         }
-        T v[2][kPer];
+    }
+    for (; t < n_tiles; t += 2 * nw) {
+        // first half of the next pass's descriptors
+        int rn[2] = {0, 0}, cn[2] = {0, 0}, trn[2] = {0, 0};
+        int64_t son[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int ne = nr[h] * nc[h];
-            // row i of the transposed tile from e / nc: (e + 1/2) / nc is at least 1/(2 nc) away
-            // from an integer, far more than the float error for e < 1024
-            const float rc = 1.0f / (float)max(nc[h], 1);
+            const int64_t x = t + (2 + h) * nw;
+            if (x < n_tiles) {
+                rn[h] = tile_row[x];
+                cn[h] = tile_col[x];
+                trn[h] = trans[x];
+                son[h] = tile_off[x];
+            }
+        }
+        // second half, between this pass's loads and stores
+        int nrn[2] = {0, 0}, ncn[2] = {0, 0};
+        int64_t don[2] = {0, 0};
+        auto mid = [&]() {
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int e = lane + 64 * k;
-                if (e < ne) {
-                    const int i = (int)(((float)e + 0.5f) * rc), j = e - i * nc[h];
-                    v[h][k] = in[so[h] + (int64_t)j * nr[h] + i];
+            for (int h = 0; h < 2; ++h) {
+                if (t + (2 + h) * nw < n_tiles) {
+                    nrn[h] = nfun[rn[h]];
+                    ncn[h] = nfun[cn[h]];
+                    don[h] = tile_off[trn[h]];
                 }
             }
-        }
+        };
+        const int ne = max(nr[0] * nc[0], nr[1] * nc[1]);
+        if (ne <= 64) transpose_pass<T, 1>(lane, nr, nc, in, so, out, dof, mid);
+        else if (ne <= 128) transpose_pass<T, 2>(lane, nr, nc, in, so, out, dof, mid);
+        else if (ne <= 256) transpose_pass<T, 4>(lane, nr, nc, in, so, out, dof, mid);
+        else if (ne <= 512) transpose_pass<T, 8>(lane, nr, nc, in, so, out, dof, mid);
+        else transpose_pass<T, kMax * kMax / 64>(lane, nr, nc, in, so, out, dof, mid);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int ne = nr[h] * nc[h];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int e = lane + 64 * k;
-                if (e < ne) out[dof[h] + e] = v[h][k];
-            }
+            nr[h] = nrn[h];
+            nc[h] = ncn[h];
+            so[h] = son[h];
+            dof[h] = don[h];
         }
     }
 }
