@@ -31,7 +31,18 @@
  *   SPM_F64       double[n_stored]
  *   SPM_F32SPLIT  float hi[n_stored] followed by float lo[n_stored]
  *                 (x = hi + lo, hi = fl32(x), lo = fl32(x - hi)); arithmetic in
- *                 FP32 with error-free products and compensated sums.
+ *                 FP32 with error-free products and compensated sums.  The masked
+ *                 product on a pattern planned with cluster levels (every cluster
+ *                 size even, unit classes of at most 7 x 7 blocks of 16) runs on
+ *                 the bf16 matrix cores instead: every row of op(A) and column of
+ *                 op(B) is scaled, per tree level of the summation cluster, by a
+ *                 power of two and cut into four 8-bit slices that bf16 holds
+ *                 exactly; the products of slice pairs whose orders add up to at
+ *                 most 5 are summed exactly in FP32 (integers below 2^24) and
+ *                 added in FP64.  The dropped pairs and the last slice bound the
+ *                 error by about 2^-32 of the product of the row and column
+ *                 scales per term (measured relative Frobenius error against
+ *                 FP64: 5e-10 to 8e-10).
  *   SPM_F32ACC    float hi[n_stored]; FP32 products.  The masked product sums
  *                 them in FP32 over a stage (at most 32 summation indices)
  *                 and adds the stage sums in FP64; tile classes the FP32
@@ -123,10 +134,11 @@ int spm_block_pattern_upload(int64_t n, int32_t n_clusters, const int64_t *clust
  * spm_block_pattern_plan / spm_compress_pattern_plan: the same validation, tile
  * layout, transpose map and schedule as the uploads, on the host only (EPATTERN,
  * EINVAL, EUNSUPPORTED as above).  cluster_level (host, n_clusters values in
- * [0, 64), or NULL): the tree level of every cluster.  With levels the middle
- * clusters of the product are ordered level by level and no stage of the schedule
- * mixes two levels, which the split-precision product (SPM_F32SPLIT) needs to scale
- * its operands per row and level; without them SPM_F32SPLIT runs on the per-tile
+ * [0, 64), or NULL): the tree level of every cluster.  With levels the plan also
+ * holds a second copy of every unit's middle clusters, ordered level by level, with
+ * stages of one level each: the split-precision product (SPM_F32SPLIT) scales its
+ * operands per row and level and runs on that copy (the FP64 and F32ACC products
+ * keep the first order); without levels SPM_F32SPLIT runs on the per-tile
  * compensated kernel.  The handle answers spm_pattern_info, spm_pattern_tiles,
  * spm_pattern_download_csr, spm_pattern_classes and spm_pattern_workspace_bytes;
  * every compute call on it returns EINVAL until it is uploaded.

@@ -104,3 +104,21 @@ def test_planned_pattern_rejects_compute(S):
     rp, col = pat.download_csr()
     orp, ocol = pattern.entry_csr(ob, blocks)
     assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+
+
+def test_split_parity_cases_cover_both_paths(S):
+    """The split-precision product runs on the matrix cores when the pattern carries
+    cluster levels, every cluster size is even and no unit class exceeds 7 x 7 blocks,
+    else on the per-tile compensated kernel.  The GPU parity cases of the product
+    (tests/test_gpu_parity.py, PRODUCT_CASES) must exercise both."""
+    from test_gpu_parity import PRODUCT_CASES
+    on_cores = []
+    for kind, n, leaf, q, eta, seed in PRODUCT_CASES:
+        t = S.Tree(synth.workload_points(kind, n, seed), leaf, q)
+        arr = t.arrays()
+        rp, col = t.block_pattern(eta)
+        pat = S.Pattern.plan_blocks(n, arr["cluster_start"], rp, col, levels=arr["level"])
+        even = bool(np.all(np.diff(arr["cluster_start"]) % 2 == 0))
+        small = all(c["row_blocks"] <= 7 and c["col_blocks"] <= 7 for c in pat.classes())
+        on_cores.append(even and small)
+    assert any(on_cores) and not all(on_cores), on_cores
