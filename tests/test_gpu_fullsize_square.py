@@ -1,5 +1,5 @@
 """Parity on the million-point square at full size, in the launch configuration
-``bench.py --workload product_2d`` times.
+``bench.py`` times by default.
 
 Workload: N = 1048576 points uniform in [0,1]^2 (seed 3), Matern nu = 3/2,
 l = 0.1, scaled by 1/N, degree 2 (m = 6), leaf 32, eta = 1.6: 3.8e7 tiles and
