@@ -2347,113 +2347,110 @@ __device__ inline void buf_store(__amdgpu_buffer_rsrc_t r, int off, typename Buf
         __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
 }
 
-// One pass of the transpose over two tiles with KP entries per lane (KP * 64 >= both sizes):
-// every access goes through the tile's own buffer resource, lanes past the end of a tile get
-// an offset beyond it (their loads return 0, their stores are dropped by the range check), so
-// the pass has no branch and each store waits only for its own load.  mid() runs between the
-// loads and the stores (the next pass's descriptors).
-template <typename T, int KP, typename Mid>
-__device__ inline void transpose_pass(int lane, const int (&nr)[2], const int (&nc)[2], const T *in,
-                                      const int64_t (&so)[2], T *out, const int64_t (&dof)[2], Mid mid)
+// out = the tiles of in, each transposed into the place of its mirror tile.  One
+// wavefront per run of kTrRun consecutive tiles: lane k loads the descriptors of tile
+// t0 + k (one coalesced load per table) into LDS.  The run's input is contiguous in
+// storage; it is staged through LDS kTrStage entries (whole tiles) at a time, read in
+// order (coalesced, through a buffer resource of the run's extent, so lanes past its end
+// read 0 without a branch), and every mirror tile is then written in order (coalesced),
+// tile by tile, each lane gathering its entry from LDS.  Staged entry q sits at q + q / 32, so the gathers (stride n_rows)
+// spread over the banks.
+constexpr int kTrRun = 64;
+constexpr int kTrStage = 1024;
+constexpr int kTrUnroll = 16;
+static_assert(kTrStage >= kMax * kMax, "a staged group holds at least one whole tile");
+// Four independent wavefronts per workgroup (a 64-thread workgroup would be held to four
+// per SIMD by the workgroup slots); each has its own LDS and orders its LDS accesses by
+// wavefront-scope fences only.
+__device__ inline void wave_sync()
 {
-    using Word = typename BufWord<T>::type;
-    Word v[2][KP];
-    __amdgpu_buffer_rsrc_t rout[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int ne = nr[h] * nc[h];
-        const __amdgpu_buffer_rsrc_t rin =
-            __builtin_amdgcn_make_buffer_rsrc((void *)(in + so[h]), 0, ne * (int)sizeof(T), kBufWord3);
-        rout[h] = __builtin_amdgcn_make_buffer_rsrc((void *)(out + dof[h]), 0, ne * (int)sizeof(T), kBufWord3);
-        // row i of the transposed tile from e / nc: (e + 1/2) / nc is at least 1/(2 nc) away
-        // from an integer, far more than the float error for e < 1024
-        const float rc = 1.0f / (float)max(nc[h], 1);
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            const int e = lane + 64 * k;
-            const int i = (int)(((float)e + 0.5f) * rc), j = e - i * nc[h];
-            v[h][k] = buf_load<T>(rin, e < ne ? (j * nr[h] + i) * (int)sizeof(T) : kBufOutside);
-        }
-    }
-    mid();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int ne = nr[h] * nc[h];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            const int e = lane + 64 * k;
-            buf_store<T>(rout[h], e < ne ? e * (int)sizeof(T) : kBufOutside, v[h][k]);
-        }
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-// out = the tiles of in, each transposed into the place of its mirror tile.  One wavefront
-// per tile, two tiles per pass: the output entries are written in order (coalesced) and
-// gathered from the input tile (at most 32 x 32 entries, so a wavefront's gathers stay
-// inside a few cache lines of one small tile).  The tile descriptors of the next pass are
-// loaded while the current pass's gathers are in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(int64_t n_tiles, const int64_t *__restrict__ tile_off,
-                                                   const int32_t *__restrict__ tile_row,
-                                                   const int32_t *__restrict__ tile_col,
-                                                   const int32_t *__restrict__ trans, const int32_t *__restrict__ nfun,
-                                                   const T *__restrict__ in, T *__restrict__ out)
+                                                  const int32_t *__restrict__ tile_row,
+                                                  const int32_t *__restrict__ tile_col,
+                                                  const int32_t *__restrict__ trans, const int32_t *__restrict__ nfun,
+                                                  const T *__restrict__ in, T *__restrict__ out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // descriptors of the pass (tiles t and t + nw): sizes and input / output offsets
-    int nr[2] = {0, 0}, nc[2] = {0, 0};
-    int64_t so[2] = {0, 0}, dof[2] = {0, 0};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int64_t x = t + h * nw;
-        if (x < n_tiles) {
-            nr[h] = nfun[tile_row[x]];
-            nc[h] = nfun[tile_col[x]];
-            so[h] = tile_off[x];
-            dof[h] = tile_off[trans[x]];
+    using Word = typename BufWord<T>::type;
+    __shared__ int32_t sh_off[4][kTrRun + 1]; // tile starts relative to the run's first entry
+    __shared__ int64_t sh_dst[4][kTrRun];     // output offset of the mirror tile
+    __shared__ int32_t sh_nr[4][kTrRun], sh_nc[4][kTrRun];
+    __shared__ float sh_rnc[4][kTrRun];
+    __shared__ Word sh_stage[4][kTrStage + kTrStage / 32];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t *s_off = sh_off[w], *s_nr = sh_nr[w], *s_nc = sh_nc[w];
+    int64_t *s_dst = sh_dst[w];
+    float *s_rnc = sh_rnc[w];
+    Word *stage = sh_stage[w];
+    for (int64_t t0 = ((int64_t)blockIdx.x * 4 + w) * kTrRun; t0 < n_tiles; t0 += (int64_t)gridDim.x * 4 * kTrRun) {
+        const int m = (int)min((int64_t)kTrRun, n_tiles - t0);
+        const int64_t base = tile_off[t0];
+        if (lane < m) {
+            const int64_t t = t0 + lane;
+            const int nc = nfun[tile_col[t]];
+            s_off[lane] = (int32_t)(tile_off[t] - base);
+            s_nr[lane] = nfun[tile_row[t]];
+            s_nc[lane] = nc;
+            s_rnc[lane] = 1.0f / (float)max(nc, 1);
+            s_dst[lane] = tile_off[trans[t]];
         }
-    }
-    for (; t < n_tiles; t += 2 * nw) {
-        // first half of the next pass's descriptors
-        int rn[2] = {0, 0}, cn[2] = {0, 0}, trn[2] = {0, 0};
-        int64_t son[2] = {0, 0};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t x = t + (2 + h) * nw;
-            if (x < n_tiles) {
-                rn[h] = tile_row[x];
-                cn[h] = tile_col[x];
-                trn[h] = trans[x];
-                son[h] = tile_off[x];
+        if (lane == 0) s_off[m] = (int32_t)(tile_off[t0 + m] - base);
+        wave_sync();
+        const int E = s_off[m];                  // entries of the run (at most kTrRun * 1024)
+        const __amdgpu_buffer_rsrc_t rin =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(in + base), 0, E * (int)sizeof(T), kBufWord3);
+        // groups of whole tiles [ka, kb) with at most kTrStage entries (a tile has at most
+        // kMax * kMax); the next group's loads are in flight while a group is written out
+        auto group_end = [&](int ka) {
+            int lo = ka + 1, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] - s_off[ka] <= kTrStage) lo = mid;
+                else hi = mid - 1;
             }
-        }
-        // second half, between this pass's loads and stores
-        int nrn[2] = {0, 0}, ncn[2] = {0, 0};
-        int64_t don[2] = {0, 0};
-        auto mid = [&]() {
+            return lo;
+        };
+        Word v[kTrUnroll];
+        auto load_group = [&](int ka, int kb) {
+            const int g0 = s_off[ka], G = s_off[kb] - g0;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (t + (2 + h) * nw < n_tiles) {
-                    nrn[h] = nfun[rn[h]];
-                    ncn[h] = nfun[cn[h]];
-                    don[h] = tile_off[trn[h]];
-                }
+            for (int u = 0; u < kTrUnroll; ++u) {
+                const int q = 64 * u + lane;
+                v[u] = buf_load<T>(rin, q < G ? (g0 + q) * (int)sizeof(T) : kBufOutside);
             }
         };
-        const int ne = max(nr[0] * nc[0], nr[1] * nc[1]);
-        if (ne <= 64) transpose_pass<T, 1>(lane, nr, nc, in, so, out, dof, mid);
-        else if (ne <= 128) transpose_pass<T, 2>(lane, nr, nc, in, so, out, dof, mid);
-        else if (ne <= 256) transpose_pass<T, 4>(lane, nr, nc, in, so, out, dof, mid);
-        else if (ne <= 512) transpose_pass<T, 8>(lane, nr, nc, in, so, out, dof, mid);
-        else transpose_pass<T, kMax * kMax / 64>(lane, nr, nc, in, so, out, dof, mid);
+        int ka = 0, kb = group_end(0);
+        load_group(ka, kb);
+        while (ka < m) {
+            const int g0 = s_off[ka], G = s_off[kb] - g0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            nr[h] = nrn[h];
-            nc[h] = ncn[h];
-            so[h] = son[h];
-            dof[h] = don[h];
+            for (int u = 0; u < kTrUnroll; ++u) {
+                const int q = 64 * u + lane;
+                if (q < G) stage[q + (q >> 5)] = v[u];
+            }
+            wave_sync();
+            const int ka2 = kb, kb2 = kb < m ? group_end(kb) : kb;
+            if (ka2 < m) load_group(ka2, kb2);
+            for (int k = ka; k < kb; ++k) {
+                const int nr = s_nr[k], nc = s_nc[k], off = s_off[k] - g0;
+                const float rnc = s_rnc[k];
+                T *dst = out + s_dst[k];
+                for (int l = lane; l < nr * nc; l += 64) {
+                    // output entry (i, j) of the mirror tile at l = i * nc + j; row i from l / nc:
+                    // (l + 1/2) / nc is at least 1/(2 nc) away from an integer, far more than the
+                    // float error for l < 1024
+                    const int i = (int)(((float)l + 0.5f) * rnc), j = l - i * nc;
+                    const int p = off + j * nr + i;             // staged input entry (i, j)
+                    dst[l] = __builtin_bit_cast(T, stage[p + (p >> 5)]);
+                }
+            }
+            wave_sync();
+            ka = ka2;
+            kb = kb2;
         }
     }
 }
@@ -2622,7 +2619,7 @@ int launch_gemm_abt(spm_pattern p, const double *A, const double *B, double *C, 
 template <typename T>
 int launch_transpose(spm_pattern p, const T *in, T *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_transpose<T>, dim3(grid1d(p->n_tiles, 8, 16384)), dim3(256), 0, s, p->n_tiles,
+    hipLaunchKernelGGL(k_transpose<T>, dim3(grid1d(p->n_tiles, 4 * kTrRun, 16384)), dim3(256), 0, s, p->n_tiles,
                        p->d_tile_off.ptr, p->d_tile_row.ptr, p->d_tile_col.ptr, p->d_trans.ptr, p->d_nfun.ptr, in, out);
     SPM_HIP(hipGetLastError());
     return SPM_OK;
