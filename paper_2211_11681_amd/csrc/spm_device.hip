@@ -1783,15 +1783,21 @@ constexpr int kOzSlices = 4;
 constexpr int kOzNoExp = -100000;      // a row and level without a nonzero value
 
 // One workgroup per block row r of the operand view V (rows of op(A), or columns of op(B)
-// as rows of op(B)^T); its waves take the row's tiles in turn, the lanes of a wave the
-// elements of a tile.  Element (i, k) of view tile t = (r, mu) is read from the source
-// tile t, column-major (i, k) at k n_r + i (rowsrc = 0), or from the source tile trans[t]
-// = (mu, r), column-major (k, i) at i n_mu + k (rowsrc = 1).  Pass 1 forms e(i, L) in LDS
-// (integer maxima: the result does not depend on the order); pass 2 writes the slices of
-// element (i, k) at position d = tile_off[trans t] + i n_mu + k (the transposed tile, rows
-// k-contiguous): the k pair (d, d + 1), d even, is 16 bytes holding (sigma_s(d),
-// sigma_s(d + 1)) for s = 1..4.  Every cluster size is even.
+// as rows of op(B)^T).  The descriptors of the row's tiles are loaded kSliceBatch at a time,
+// one per thread, into LDS; the waves then take the batch's tiles in turn, the lanes of a
+// wave the elements of a tile.  Element (i, k) of view tile t = (r, mu) is read from the
+// source tile t, column-major (i, k) at k n_r + i (rowsrc = 0), or from the source tile
+// trans[t] = (mu, r), column-major (k, i) at i n_mu + k (rowsrc = 1).  Pass 1 reads every
+// source tile in storage order and forms e(i, L) in LDS (integer maxima: the result does
+// not depend on the order); pass 2 writes the slices of element (i, k) at position
+// d = tile_off[trans t] + i n_mu + k (the transposed tile, rows k-contiguous): the k pair
+// (d, d + 1), d even, is 16 bytes holding (sigma_s(d), sigma_s(d + 1)) for s = 1..4.
+// Every cluster size is even.  Quotients by a cluster size (at most 32) of an index below
+// 1024 are taken as (e + 1/2) / n in float, which is at least 1/(2 n) away from an integer.
 constexpr int kSliceWaves = 8;
+constexpr int kSliceBatch = 64 * kSliceWaves;
+
+__device__ inline int small_quot(int e, float rcp) { return (int)(((float)e + 0.5f) * rcp); }
 
 __global__ __launch_bounds__(64 * kSliceWaves) void k_oz_slice(int32_t nc, int32_t nlev, int rowsrc, int64_t ns,
                                                   const int64_t *__restrict__ blk_rp, const int32_t *__restrict__ tile_col,
@@ -1801,51 +1807,77 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_oz_slice(int32_t nc, int32
                                                   uint4 *__restrict__ S, int32_t *__restrict__ expo)
 {
     extern __shared__ int emax[];            // kMax x nlev
+    __shared__ int64_t b_src[kSliceBatch], b_dst[kSliceBatch];
+    __shared__ int32_t b_nm[kSliceBatch], b_lev[kSliceBatch];
     const int r = blockIdx.x;
     if (r >= nc) return;
     const int nr = nfun[r];
     if (nr == 0) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const float rnr = 1.0f / (float)nr;
     for (int x = threadIdx.x; x < nr * nlev; x += blockDim.x) emax[x] = kOzNoExp;
-    __syncthreads();
     const int64_t t0 = blk_rp[r], t1 = blk_rp[r + 1];
-    for (int64_t t = t0 + wave; t < t1; t += kSliceWaves) {
-        const int mu = tile_col[t], nm = nfun[mu], L = clevel[mu];
-        const int64_t base = rowsrc ? tile_off[trans[t]] : tile_off[t];
-        for (int e = lane; e < nr * nm; e += 64) {
-            const int i = e / nm, k = e - i * nm;
-            const int64_t q = base + (rowsrc ? (int64_t)i * nm + k : (int64_t)k * nr + i);
-            const double x = (double)X[q] + (double)X[ns + q];
-            if (x != 0.0) atomicMax(&emax[i * nlev + L], ilogb(fabs(x)) + 1);
+    auto load_batch = [&](int64_t tb) {
+        __syncthreads();                      // the previous batch is consumed
+        const int64_t t = tb + threadIdx.x;
+        if (t < t1) {
+            const int mu = tile_col[t];
+            const int64_t d0 = tile_off[trans[t]];
+            b_nm[threadIdx.x] = nfun[mu];
+            b_lev[threadIdx.x] = clevel[mu];
+            b_dst[threadIdx.x] = d0;
+            b_src[threadIdx.x] = rowsrc ? d0 : tile_off[t];
+        }
+        __syncthreads();
+        return (int)min((int64_t)kSliceBatch, t1 - tb);
+    };
+    for (int64_t tb = t0; tb < t1; tb += kSliceBatch) {
+        const int nb = load_batch(tb);
+        for (int b = wave; b < nb; b += kSliceWaves) {
+            const int nm = b_nm[b], L = b_lev[b];
+            const float rnm = 1.0f / (float)max(nm, 1);
+            const float *xs = X + b_src[b];
+            for (int e = lane; e < nr * nm; e += 64) {
+                const int i = rowsrc ? small_quot(e, rnm) : e - small_quot(e, rnr) * nr;
+                const double x = (double)xs[e] + (double)xs[ns + e];
+                if (x != 0.0) {
+                    const int ex = ilogb(fabs(x)) + 1;
+                    int *slot = &emax[i * nlev + L];
+                    if (ex > *slot) atomicMax(slot, ex);
+                }
+            }
         }
     }
     __syncthreads();
     for (int x = threadIdx.x; x < nr * nlev; x += blockDim.x) expo[(cstart[r] + x / nlev) * nlev + x % nlev] = emax[x];
-    for (int64_t t = t0 + wave; t < t1; t += kSliceWaves) {
-        const int mu = tile_col[t], nm = nfun[mu], L = clevel[mu];
-        const int np = nm >> 1;
-        const int64_t d0 = tile_off[trans[t]];
-        const int64_t base = rowsrc ? d0 : tile_off[t];
-        for (int e = lane; e < nr * np; e += 64) {
-            const int i = e / np, k = 2 * (e - i * np);
-            const int ex = emax[i * nlev + L];
-            const int sh = ex == kOzNoExp ? 0 : -ex;
-            uint32_t w[kOzSlices];
+    for (int64_t tb = t0; tb < t1; tb += kSliceBatch) {
+        const int nb = load_batch(tb);
+        for (int b = wave; b < nb; b += kSliceWaves) {
+            const int nm = b_nm[b], L = b_lev[b];
+            const int np = nm >> 1;
+            const float rnp = 1.0f / (float)max(np, 1);
+            const int64_t d0 = b_dst[b], base = b_src[b];
+            for (int e = lane; e < nr * np; e += 64) {
+                const int i = small_quot(e, rnp), k = 2 * (e - i * np);
+                const int ex = emax[i * nlev + L];
+                const int sh = ex == kOzNoExp ? 0 : -ex;
+                uint32_t w[kOzSlices];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int64_t q = base + (rowsrc ? (int64_t)i * nm + k + h : (int64_t)(k + h) * nr + i);
-                double y = ldexp((double)X[q] + (double)X[ns + q], sh);
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t q = base + (rowsrc ? (int64_t)i * nm + k + h : (int64_t)(k + h) * nr + i);
+                    double y = ldexp((double)X[q] + (double)X[ns + q], sh);
 #pragma unroll
-                for (int sl = 0; sl < kOzSlices; ++sl) {
-                    y = y * 256.0;
-                    const double sg = rint(y);
-                    y = y - sg;
-                    const uint32_t bits = __float_as_uint((float)sg) >> 16;     // exact in bf16
-                    w[sl] = h == 0 ? bits : (w[sl] | bits << 16);
+                    for (int sl = 0; sl < kOzSlices; ++sl) {
+                        y = y * 256.0;
+                        const double sg = rint(y);
+                        y = y - sg;
+                        const uint32_t bits = __float_as_uint((float)sg) >> 16;     // exact in bf16
+                        w[sl] = h == 0 ? bits : (w[sl] | bits << 16);
+                    }
                 }
+                S[(d0 + (int64_t)i * nm + k) >> 1] = make_uint4(w[0], w[1], w[2], w[3]);
             }
-            S[(d0 + (int64_t)i * nm + k) >> 1] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
