@@ -2181,9 +2181,12 @@ __global__ __launch_bounds__(WAVES * 64, SHARE ? 4 : 1) void k_mgemm_oz(GroupArg
 //    16 rb + l%16 and X at column cc0 + 16 cb + l%16, both at piece columns
 //    l/16 + 4s (s = 0..3), so every value of A and X is loaded once.
 //  - n_nu <= 8 (where a 16-row MFMA would be mostly padding): plain FMAs.  Lane l takes
-//    piece column l%16 of each chunk and X columns l/16 + 4m; it loads its column of A
-//    once and keeps n_nu x 4 CB sums, folded over the 16 column lanes at the end.
-constexpr int kSpmmWaves = 8;
+//    piece column l%16 of each chunk and X columns l/16 + 4m, and keeps n_nu x 4 CB sums,
+//    folded over the 16 column lanes at the end; with at most four columns of X, lane l
+//    takes piece column l of each 64-column step and all columns of X, so each entry of
+//    A is loaded once.
+// Four waves per workgroup, so that three workgroups fit on a CU.
+constexpr int kSpmmWaves = 4;
 
 // load at a uniform base plus a 32-bit byte offset (one VGPR per address)
 __device__ __forceinline__ double ld_off(const double *base, uint32_t byte_off)
@@ -2317,7 +2320,7 @@ __device__ __forceinline__ void spmm_thin(int64_t q, int64_t p1, int nr, int64_t
 }
 
 template <int CB>
-__global__ __launch_bounds__(64 * kSpmmWaves) void k_spmm(int32_t nc, int64_t n, int32_t r,
+__global__ __launch_bounds__(64 * kSpmmWaves, 3) void k_spmm(int32_t nc, int64_t n, int32_t r,
                                                           const int64_t *__restrict__ pc_rp,
                                                           const int64_t *__restrict__ pc_off,
                                                           const int64_t *__restrict__ pc_g,
