@@ -20,9 +20,12 @@ the tile structure) per call divided by its average duration from HIP events on
 the launch stream, against the dense FP64 MFMA peak; traffic = HBM bytes per call
 from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (null once the
 device code or schedule differs from the one the counters were taken on).
-cpu_baseline: the oracle's sorted-merge product timed on the host cores over a
-level-stratified sample of output tiles, extrapolated to the whole product by
-exact multiply-adds.
+CPU leg (the only part of this file that runs the oracle, skipped with
+--no-cpu-baseline): on the host cores, the FP64 oracle computes reference entries
+of P_S(K K) for a sample of output positions (oracle_sample, the error of every form
+against them), and its sorted-merge product is timed over a level-stratified sample
+of output tiles and extrapolated to the whole product by exact multiply-adds
+(cpu_baseline).
 
 --workload product_cube3 runs the same measurement on N = 131072 points in the
 unit cube (exponential kernel, l = 0.3, degree 1, leaf 32, eta = 1.0, seed 2),
@@ -58,9 +61,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None, help="override N (testing only)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU leg (the oracle's reference entries and the CPU baseline)")
     ap.add_argument("--no-split", action="store_true")
-    ap.add_argument("--no-oracle-sample", action="store_true")
+    ap.add_argument("--no-oracle-sample", action="store_true",
+                    help="skip only the oracle's reference entries of the CPU leg")
     ap.add_argument("--split-modes", default="f32split,f32acc", help="comma-separated FP32 forms to time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy K once (n_stored doubles read and written) so that "
@@ -193,7 +198,7 @@ def cpu_baseline(ot, ob, eta, total_macs, nnz, threads, seed=77, clusters_per_le
                       f"{t_full:.1f} s"}
 
 
-def oracle_sampled_rows(pts, w, leaves_at=(7, 2), levels=(13, 11)):
+def cpu_leg_sampled_entries(pts, w, leaves_at=(7, 2), levels=(13, 11)):
     """Oracle rows of K^eta = P_S(T K T^T) for a small sample of basis functions (the
     first and last function of two leaves and of their ancestors on the given levels),
     and the sampled pairs (i, j) of S with the reference entries
@@ -699,11 +704,12 @@ def product_main(args, w, with_axpy):
     }
     ref_norm = S.sqdist(pat, C).item() ** 0.5
 
-    # oracle rows for sampled entries (FP64 oracle, independent of the library)
+    # CPU leg, first part: oracle rows for sampled entries (FP64 oracle on the host,
+    # independent of the library)
     sample = None
-    if full and not args.no_oracle_sample:
+    if full and not args.no_cpu_baseline and not args.no_oracle_sample:
         t1 = time.perf_counter()
-        ot, ob, ij, ref = oracle_sampled_rows(pts, w)
+        ot, ob, ij, ref = cpu_leg_sampled_entries(pts, w)
         pos = torch.from_numpy(tile_positions(pat, ob.cluster_start, ij)).cuda()
         got = C[pos].cpu().numpy()
         e64 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
@@ -771,6 +777,7 @@ def product_main(args, w, with_axpy):
             torch.cuda.empty_cache()
             print(f"[bench] {prec}: {ms:.3f} ms x {reps}, rel err vs FP64 {err:.3e}", file=sys.stderr, flush=True)
         del Kcur
+    # CPU leg, second part: the oracle's product timed on the host cores
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("SPM_CPU_THREADS", os.cpu_count() or 1))
         if sample is not None:
