@@ -1543,8 +1543,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_mgemm_thin(GroupArgs g, const do
     }
 }
 
-// Transpose of an S-matrix: tile (c, r) of X^T is (X_{r,c})^T.  One block per tile,
-// staged through LDS so that reads and writes are both contiguous.
 // ---------------------------------------------------------------- FP32-accumulate product
 // F32ACC: the same unit schedule with FP32 operands and v_mfma_f32_16x16x4f32.  Each
 // stage's MFMA sums (FP32, 32 k rows) are added into FP64 accumulators; the result is
