@@ -21,6 +21,10 @@ fall from 5e-7 (level 11) to 2e-10 (leaves).  A bound relative to each row's
 own norm would test the conditioning of the exact construction, not the
 arithmetic of either side.
 
+The same sampled entries check the two FP32 forms of the product (the FP32-split
+product on the matrix cores, relative Frobenius error over the sample <= 1e-8; F32ACC
+<= 1e-6).
+
 The construction of the million-point problem takes about two minutes on the GPU
 host (tree, pattern, schedule and the O(N^2) compression).
 """
@@ -122,3 +126,28 @@ def test_square_full_size_sampled_entries():
           flush=True)
     assert max(kpos) >= 2 ** 32
     assert kfro < 1e-12 and kent < 1e-12
+
+    # the FP32 forms of the same product at the same sampled entries (the FP32-split
+    # product runs on the matrix cores here: levels in the plan, even cluster sizes),
+    # against the oracle: relative Frobenius error over the sample <= 1e-8 (F32SPLIT)
+    # and <= 1e-6 (F32ACC), the bounds of the small parity cases
+    del C
+    torch.cuda.empty_cache()
+    pos_t = torch.from_numpy(pos).cuda()
+    Kcur, cur = K, "f64"
+    del K
+    for prec, tol in (("f32split", 1e-8), ("f32acc", 1e-6)):
+        print(f"case: full-size product in {prec}", flush=True)
+        Ks = spm.convert(pat, Kcur, cur, prec)
+        del Kcur
+        torch.cuda.empty_cache()
+        Kcur, cur = Ks, prec
+        Cs = spm.masked_gemm(pat, Ks, Ks, prec=prec)
+        g = Cs[pos_t].double()
+        if prec == "f32split":
+            g = g + Cs[pat.n_stored + pos_t].double()
+        err = np.linalg.norm(g.cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(f"{prec}: {len(pairs)} sampled entries, rel Frobenius {err:.3e}", flush=True)
+        assert err <= tol, (prec, err)
+        del Cs, Ks
+        torch.cuda.empty_cache()
