@@ -12,7 +12,8 @@ output tiles have the longest middle lists and the most stages.
 Sampled entries of K^eta and of C are compared one by one.
 
 Tolerance per entry: 1e-12 * ||K_i|| ||K_j|| for C (the Cauchy-Schwarz scale of
-the sum) and 1e-12 * ||K_i|| for K.
+the sum) and 1e-12 * ||K_i|| for K.  The FP32 forms of the product are held at the
+same entries to a relative Frobenius error of 1e-8 (FP32-split) and 1e-6 (F32ACC).
 
 The same run checks the two operations that the error measure e_F uses, as the
 benchmark runs them at this size: rows of Y = K^eta X for a uniform block X of 10
@@ -103,6 +104,19 @@ def test_product_full_size_sampled_entries():
     err = np.abs(got - ref) / scale
     print(f"C: {len(pairs)} sampled entries, max error / (|K_i||K_j|) = {err.max():.3e}", flush=True)
     assert err.max() < 1e-12
+
+    # the FP32 forms of the product at the same entries (relative Frobenius error over
+    # the sample: FP32-split on the matrix cores <= 1e-8, F32ACC <= 1e-6)
+    for prec, tol in (("f32split", 1e-8), ("f32acc", 1e-6)):
+        Ks = spm.convert(pat, K, "f64", prec)
+        Cs = spm.masked_gemm(pat, Ks, Ks, prec=prec)
+        g = Cs[idx].double()
+        if prec == "f32split":
+            g = g + Cs[pat.n_stored + idx].double()
+        e32 = np.linalg.norm(g.cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(f"{prec}: {len(pairs)} sampled entries, rel Frobenius {e32:.3e}", flush=True)
+        assert e32 <= tol, (prec, e32)
+        del Ks, Cs
 
     # K entries: 64 seeded columns of each sampled row
     kpos, kref, kscale = [], [], []
